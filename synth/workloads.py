@@ -1,0 +1,157 @@
+"""Seeded workloads at the shapes of the paper's sensor (a 64-beam spinning
+lidar swept at 10 Hz; keyframes of 1024x128 and 2048x256) and of the five
+benchmark configurations of this project.
+
+Each function returns plain numpy data: FP32 range images, FP64 ground-truth
+poses and the geometry.  Nothing here computes normals, projections or
+registrations.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import Geom, inv, lidar_geom, outdoor_scene, render, room_scene, rot_x, rot_y, rot_z, se3
+
+DEG = math.pi / 180.0
+
+
+def _unit_horizontal(rng):
+    a = rng.uniform(0, 2 * math.pi)
+    return np.array([math.cos(a), math.sin(a), 0.0])
+
+
+# ----------------------------------------------------------------------------
+# configuration 0: one 64x512 scan against one 64x512 keyframe in the box room
+# ----------------------------------------------------------------------------
+
+def config0(scene_seed: int = 0, noise_seed: int = 1, rows: int = 64, cols: int = 512, noise: float = 0.01,
+            with_boxes: bool = True, want_normals: bool = False, dtype=np.float32):
+    """Box room 20x10x4 m with 5 boxes; keyframe sensor at (0, 0, 1.5) m; the
+    scan is displaced by 2 deg yaw, 1 deg roll and 0.1 m along a seeded
+    horizontal direction.  Returns dict(geom, kf, scan, T_gt, T_world_kf, ...)
+    where T_gt = T_kf_scan."""
+    g = lidar_geom(rows, cols)
+    rng = np.random.Generator(np.random.PCG64(scene_seed + 7919))
+    d = _unit_horizontal(rng)
+    T_w_kf = se3(np.eye(3), [0.0, 0.0, 1.5])
+    T_gt = se3(rot_z(2 * DEG) @ rot_x(1 * DEG), 0.1 * d)
+    T_w_s = T_w_kf @ T_gt
+    scene = room_scene(scene_seed, sensor_positions=[T_w_kf[:3, 3], T_w_s[:3, 3]], with_boxes=with_boxes)
+    out = dict(geom=g, T_gt=T_gt, T_world_kf=T_w_kf, T_world_scan=T_w_s, scene=scene)
+    if want_normals:
+        out["kf"], out["kf_normals"] = render(scene, g, T_w_kf, noise, noise_seed, want_normals=True, dtype=dtype)
+        out["scan"], out["scan_normals"] = render(scene, g, T_w_s, noise, noise_seed + 1, want_normals=True,
+                                                  dtype=dtype)
+    else:
+        out["kf"] = render(scene, g, T_w_kf, noise, noise_seed, dtype=dtype)
+        out["scan"] = render(scene, g, T_w_s, noise, noise_seed + 1, dtype=dtype)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# configuration 1: sensor-scale outdoor sequence
+# ----------------------------------------------------------------------------
+
+def _ground_z(scene, xy):
+    return float(scene.ground_height(np.asarray(xy, float).reshape(1, 2))[0])
+
+
+def random_motion(rng, max_angle, max_trans, yaw_frac=0.8, max_z=None):
+    """A rigid motion with rotation angle <= max_angle (mostly yaw) and
+    translation length <= max_trans."""
+    yaw = rng.uniform(-1, 1) * max_angle * yaw_frac
+    rem = math.sqrt(max(0.0, max_angle ** 2 - yaw ** 2))
+    roll = rng.uniform(-1, 1) * rem / math.sqrt(2)
+    pitch = rng.uniform(-1, 1) * rem / math.sqrt(2)
+    R = rot_z(yaw) @ rot_y(pitch) @ rot_x(roll)
+    t = rng.normal(size=3)
+    if max_z is not None:
+        t[2] = 0.0
+    t = t / np.linalg.norm(t) * rng.uniform(0.2, 1.0) * max_trans
+    if max_z is not None:
+        t[2] = rng.uniform(-max_z, max_z)
+    return se3(R, t)
+
+
+def config1(seed: int = 11, rows: int = 128, cols: int = 1024, n_kf_scans: int = 10, path_len: float = 5.0,
+            noise: float = 0.01, max_angle=5 * DEG, max_trans=0.5, world_offset=(0.0, 0.0), dtype=np.float32):
+    """Outdoor scene; ``n_kf_scans`` scans along a ``path_len`` m path whose
+    fusion forms the keyframe (in the frame of the first scan); an extra scan
+    displaced from the last one by up to ``max_angle`` / ``max_trans``.
+
+    Returns dict(geom, kf_scans [list of ranges], T_kf_scans [list of 4x4],
+    scan, T_gt, T_init, T_world_kf, scene)."""
+    g = lidar_geom(rows, cols)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    off = np.array([world_offset[0], world_offset[1]], dtype=np.float64)
+    n = n_kf_scans
+    xs = np.linspace(0.0, path_len, n)
+    ys = 0.3 * np.sin(xs / path_len * math.pi)
+    path = np.stack([xs, ys], axis=1) + off
+    scene = outdoor_scene(seed + 1, path)
+    poses = []
+    for k in range(n):
+        heading = math.atan2(0.3 * math.pi / path_len * math.cos(xs[k] / path_len * math.pi), 1.0)
+        R = rot_z(heading + rng.uniform(-1, 1) * DEG) @ rot_y(rng.uniform(-0.5, 0.5) * DEG) @ rot_x(
+            rng.uniform(-0.5, 0.5) * DEG)
+        z = 1.8 + _ground_z(scene, path[k])
+        poses.append(se3(R, [path[k, 0], path[k, 1], z]))
+    delta = random_motion(rng, rng.uniform(0.5, 1.0) * max_angle, max_trans, max_z=0.05)
+    T_w_last = poses[-1] @ delta
+    T_w_kf = poses[0]
+    scans = [render(scene, g, P, noise, seed * 1000 + k, dtype=dtype) for k, P in enumerate(poses)]
+    scan = render(scene, g, T_w_last, noise, seed * 1000 + n, dtype=dtype)
+    T_kf_scans = [inv(T_w_kf) @ P for P in poses]
+    return dict(geom=g, kf_scans=scans, T_kf_scans=T_kf_scans, scan=scan, T_gt=inv(T_w_kf) @ T_w_last,
+                T_init=T_kf_scans[-1], T_world_kf=T_w_kf, T_world_scan=T_w_last, scene=scene)
+
+
+# ----------------------------------------------------------------------------
+# configuration 2: many independent registrations of uneven sizes
+# ----------------------------------------------------------------------------
+
+BATCH_SIZES = ((64, 512), (64, 1024), (128, 1024), (128, 2048))
+
+
+def batch_pair(k: int, base_seed: int = 1000, max_angle=10 * DEG, max_trans=1.0, sizes=BATCH_SIZES,
+               noise: float = 0.01, dtype=np.float32, size=None):
+    """Registration pair k: scene kind by a seeded coin, panorama size uniform
+    over ``sizes``, motion with yaw up to the limit, roll/pitch up to 3 deg,
+    translation in a ``max_trans`` ball with |z| <= 0.2 m."""
+    seed = base_seed + k
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows, cols = sizes[int(rng.integers(len(sizes)))] if size is None else size
+    g = lidar_geom(rows, cols)
+    outdoor = bool(rng.integers(2))
+    yaw = rng.uniform(-1, 1) * max_angle
+    roll = rng.uniform(-3, 3) * DEG
+    pitch = rng.uniform(-3, 3) * DEG
+    ang = math.sqrt(yaw * yaw + roll * roll + pitch * pitch)
+    if ang > max_angle:
+        s = max_angle / ang
+        yaw, roll, pitch = yaw * s, roll * s, pitch * s
+    t = rng.normal(size=3)
+    t[2] = 0.0
+    t = t / (np.linalg.norm(t) + 1e-12) * max_trans * rng.uniform(0, 1) ** (1 / 3)
+    t[2] = rng.uniform(-0.2, 0.2)
+    delta = se3(rot_z(yaw) @ rot_y(pitch) @ rot_x(roll), t)
+    if outdoor:
+        kf_xy = np.array([0.0, 0.0])
+        scene = outdoor_scene(seed * 7 + 3, np.stack([kf_xy, kf_xy + t[:2]]))
+        z = 1.8 + float(scene.ground_height(kf_xy.reshape(1, 2))[0])
+        T_w_kf = se3(rot_z(rng.uniform(0, 2 * math.pi)), [kf_xy[0], kf_xy[1], z])
+    else:
+        c = np.array([rng.uniform(-3, 3), rng.uniform(-1.5, 1.5), 1.5])
+        T_w_kf = se3(rot_z(rng.uniform(-0.5, 0.5)), c)
+        T_w_s0 = T_w_kf @ delta
+        scene = room_scene(seed * 7 + 3, sensor_positions=[T_w_kf[:3, 3], T_w_s0[:3, 3]])
+    T_w_s = T_w_kf @ delta
+    kf = render(scene, g, T_w_kf, noise, seed * 2, dtype=dtype)
+    scan = render(scene, g, T_w_s, noise, seed * 2 + 1, dtype=dtype)
+    return dict(geom=g, kf=kf, scan=scan, T_gt=delta, kind=scene.kind, seed=seed)
+
+
+def batch(n: int = 256, base_seed: int = 1000, **kw):
+    return [batch_pair(k, base_seed, **kw) for k in range(n)]
