@@ -1,0 +1,202 @@
+/*
+ * upslam.h -- C ABI of the MI355X (gfx950) projective-ICP registration library.
+ *
+ * The library implements the data-parallel hot path of UPSLAM (Cowley, Miller,
+ * Taylor, "UPSLAM: Union of Panoramas SLAM", arXiv 2101.00585):
+ *   - surface normals of a panoramic range image          (Section III-A)
+ *   - registration of a sweep against a keyframe by ICP   (Section III-B, Eq. 1)
+ *     with the point-to-plane metric over projective correspondences and the
+ *     similarity filter Omega_{d,theta}
+ *   - the count-weighted keyframe update                  (Section III-C)
+ *
+ * Conventions for every call
+ *   - Device pointers are caller-owned (e.g. torch tensors), 16-byte aligned for
+ *     float4 images, and never freed or retained by the library.
+ *   - Every call is asynchronous on the given HIP stream (a hipStream_t passed as
+ *     void*; NULL = the default stream).  Results land in device memory; the
+ *     caller synchronises before reading them.  After ups_context_create no call
+ *     allocates device memory, and ups_register_scan / ups_fuse_scan /
+ *     ups_panorama_normals / ups_register_batch enqueue only kernels, so they can
+ *     be captured into a HIP graph (geometries must have been seen once outside
+ *     capture, see ups_context_create).
+ *   - One context holds the scratch space of one registration at a time: calls
+ *     on the same context must be ordered (same stream, or synchronised).
+ *   - A non-zero return is a usage or HIP error (message in ups_last_error()).
+ *     Numerical outcomes are not errors: they are reported in
+ *     ups_icp_result.status.
+ *
+ * Panorama layout: a range image is float[rows][cols] (row-major).  Row i looks
+ * along elevation el_top - i*d_el, column j along azimuth 2*pi*j/cols (column 0
+ * along +x, counter-clockwise about +z); the ray is (cos el cos az, cos el sin
+ * az, sin el) and the point is range * ray.  A range is valid iff finite and
+ * r_min < r <= r_max (compared in FP32).  A surfel image is
+ * float[rows][cols][4] = (nx, ny, nz, range): range 0 = no return, normal
+ * (0,0,0) = no normal.  Keyframe sample counts are uint16[rows][cols].
+ * A pose is T = (R, t), FP64, R row-major, mapping scan coordinates into
+ * keyframe coordinates: x_kf = R x_scan + t (the T of Equation 1, s1 in the
+ * keyframe, s2 in the sweep).
+ */
+#ifndef UPSLAM_H
+#define UPSLAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UPS_OK = 0,
+    UPS_ERR_INVALID_ARG = -1, /* bad pointer, size, geometry or parameter */
+    UPS_ERR_HIP = -2,         /* a HIP runtime call failed */
+    UPS_ERR_UNSUPPORTED = -3, /* valid request this build does not support */
+    UPS_ERR_WORKSPACE = -4    /* request exceeds what the context was created for */
+} ups_status;
+
+/* ups_icp_result.status values */
+enum {
+    UPS_CONVERGED = 0,     /* finished: stop criterion met, or fixed iteration count done */
+    UPS_MAX_ITERS = 1,     /* stop criterion > 0 was not met at level 0 */
+    UPS_DEGENERATE = 2,    /* J^T J not positive definite: pose left at the last good value */
+    UPS_NO_INLIERS = 3,    /* fewer than min_inliers correspondences: pose left unchanged */
+    UPS_FALLBACK_USED = 4  /* batch: proposal rejected, identity-initialised result kept */
+};
+
+/* ups_icp_params.precision values */
+enum {
+    UPS_PREC_KAHAN_F64 = 0, /* FP32 per pixel, Kahan-compensated FP32 per-thread sums,
+                               FP64 cross-lane/block/grid sums, FP64 solve and pose update */
+    UPS_PREC_F32 = 1        /* FP32 everywhere, including the solve and the pose update */
+};
+
+typedef struct {
+    int32_t rows, cols;
+    double el_top, d_el; /* radians */
+    double r_min, r_max; /* metres */
+} ups_geom;
+
+typedef struct {
+    double R[9]; /* row-major */
+    double t[3];
+} ups_pose;
+
+/* Normal estimation (Section III-A).  The raw normal of pixel (i, j) is the
+ * normalised cross product of the vectors from its point to the points of
+ * (i, j+1 mod cols) and (i+1, j) -- (i-1, j) on the last row -- oriented towards
+ * the sensor.  No normal when a range is invalid, when a neighbour's range
+ * differs by more than max_rel_jump * r, or when the cross product is
+ * degenerate.  Then atrous_levels passes of an edge-aware a-trous filter: 5x5
+ * B3-spline taps spaced 2^l, weights exp(-((r_q-r_p)/(sigma_r r_p))^2) *
+ * exp(-(2-2 n_p.n_q)/sigma_n^2), renormalised.  Defaults: 2, 0.5, 0.05, 0.5. */
+typedef struct {
+    int32_t atrous_levels;
+    float sigma_n, sigma_r, max_rel_jump;
+} ups_normal_params;
+
+/* Registration (Section III-B).  Coarse-to-fine over `levels` (1..4) pyramid
+ * levels (level l keeps every 2^l-th row and column); iters[l] Gauss-Newton
+ * steps at level l on the squared point-to-plane residuals of Equation 1.
+ * Omega: inlier iff both surfels are valid, |q - s1| <= d_max[l] and
+ * (R n2).n1 >= cos_theta_max.  A level ends early when stop_update_norm > 0 and
+ * the step norm |xi| falls below it.  min_inliers: fewer correspondences stop
+ * the registration with UPS_NO_INLIERS.  rows and cols must be divisible by
+ * 2^(levels-1) and cols/2^(levels-1) by 64. */
+typedef struct {
+    int32_t levels;
+    int32_t iters[4];
+    float d_max[4];
+    float cos_theta_max;
+    double stop_update_norm;
+    int32_t min_inliers;
+    int32_t precision; /* UPS_PREC_* */
+} ups_icp_params;
+
+/* Result of a registration (device memory).  T: final pose.  The quality block
+ * is evaluated at level 0 and the final pose (Section III-C): inliers over
+ * valid scan ranges, rms of inlier residuals, truncated cost sum over valid
+ * scan pixels of min(r^2, d_max[0]^2) with non-inliers counting d_max[0]^2, and
+ * the normal equations (upper triangle of J^T J row-major, J^T r) there. */
+typedef struct {
+    ups_pose T;
+    double rms, trunc_cost, inlier_ratio;
+    int64_t inliers, valid;
+    int32_t iters_run, status;
+    double JtJ[21], Jtr[6];
+    double last_update_norm;
+} ups_icp_result;
+
+/* Normal equations at a fixed pose (device memory), see ups_normal_equations. */
+typedef struct {
+    double JtJ[21], Jtr[6];
+    double sum_r2;
+    int64_t inliers, valid;
+} ups_normal_eq;
+
+/* Keyframe update (Section III-C): keyframe pixels holding c > 0 samples take a
+ * sample from the registered sweep if it passes |q - s1| <= d_max,
+ * m.n1 >= cos_theta_max and |u.n1| >= min_cos_incidence; range and normal are
+ * averaged with weights c : 1 and c <- min(c+1, max_count).  Empty keyframe
+ * pixels take the nearest (smallest |q|, then smallest scan index) scan surfel
+ * projecting onto them, with c = 1. */
+typedef struct {
+    float d_max, cos_theta_max, min_cos_incidence;
+    int32_t max_count;
+} ups_fuse_params;
+
+typedef struct ups_context ups_context;
+
+/* Create a context on `device` for panoramas of up to max_pixels pixels and
+ * batches of up to max_batch registrations whose panoramas total at most
+ * max_batch_pixels pixels (scan and keyframe each).  All device memory the
+ * library needs is allocated here.  The first use of a new panorama geometry
+ * uploads its ray tables synchronously; such a first use is rejected during
+ * stream capture (UPS_ERR_INVALID_ARG). */
+ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels, int32_t max_batch,
+                              int64_t max_batch_pixels);
+void ups_context_destroy(ups_context *ctx);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *ups_last_error(void);
+
+/* Surfel image (Section III-A) from a range image.  depth_d: float[rows][cols];
+ * surfel_d: float[rows][cols][4] output (must not alias depth_d). */
+ups_status ups_panorama_normals(ups_context *ctx, const ups_geom *g, const float *depth_d, float *surfel_d,
+                                const ups_normal_params *p, void *stream);
+
+/* Pyramid level `level` (>= 1) of a surfel image: pixel (i, j) = level-0 pixel
+ * (2^l i, 2^l j).  out_d: float[rows>>l][cols>>l][4]. */
+ups_status ups_pyramid_level(ups_context *ctx, const ups_geom *g, const float *surfel_d, int32_t level,
+                             float *out_d, void *stream);
+
+/* Register a sweep's surfel image against a keyframe's surfel image
+ * (Section III-B).  init_d: device pose to start from (may alias
+ * &result_d->T).  result_d: device ups_icp_result written by the call. */
+ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                             const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *init_d,
+                             const ups_icp_params *p, ups_icp_result *result_d, void *stream);
+
+/* Fuse a registered sweep into a keyframe in place (Section III-C).  T_d: device
+ * pose scan -> keyframe (e.g. &result_d->T).  kf_surfel_d / kf_count_d are
+ * read and written; the sweep's surfel image is only read. */
+ups_status ups_fuse_scan(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                         const ups_geom *kf_g, float *kf_surfel_d, uint16_t *kf_count_d, const ups_pose *T_d,
+                         const ups_fuse_params *p, void *stream);
+
+/* Projective correspondences at a fixed pose at level 0 (Section III-B):
+ * kf_index_d[rows*cols] = keyframe pixel index i*cols+j the scan point projects
+ * to, or -1 (no scan surfel or outside the keyframe's rows); inlier_d = 1 iff
+ * the pair passes Omega with thresholds d_max / cos_theta_max. */
+ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                               const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
+                               float cos_theta_max, int32_t *kf_index_d, uint8_t *inlier_d, void *stream);
+
+/* Gauss-Newton normal equations of Equation 1 at a fixed pose at level 0, with
+ * the given precision mode's reduction (UPS_PREC_*). */
+ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
+                                float cos_theta_max, int32_t precision, ups_normal_eq *out_d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UPSLAM_H */

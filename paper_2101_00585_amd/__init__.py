@@ -1,0 +1,350 @@
+"""Python binding of the MI355X projective-ICP library (``libupslam.so``).
+
+Argument marshalling only: every step of the registration path runs in the
+HIP kernels behind the C ABI declared in ``include/upslam.h``.  PyTorch
+supplies device memory and streams; tensors are passed by ``data_ptr()`` and
+work is enqueued on ``torch.cuda.current_stream()``.
+
+The library implements UPSLAM's (arXiv 2101.00585) per-sweep path:
+``panorama_normals`` (Section III-A), ``register_scan`` (Section III-B,
+Equation 1) and ``fuse_scan`` (Section III-C), plus ``correspondences`` and
+``normal_equations`` at a fixed pose and ``pyramid_level``.
+
+There is no CPU fallback: if the shared library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libupslam.so")
+_LIB = None
+
+STATUS = {0: "CONVERGED", 1: "MAX_ITERS", 2: "DEGENERATE", 3: "NO_INLIERS", 4: "FALLBACK_USED"}
+PREC_KAHAN_F64 = 0
+PREC_F32 = 1
+
+
+class UpsError(RuntimeError):
+    pass
+
+
+# ----------------------------------------------------------------------------
+# C structs (layouts of include/upslam.h)
+# ----------------------------------------------------------------------------
+
+class ups_geom(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("el_top", ctypes.c_double),
+                ("d_el", ctypes.c_double), ("r_min", ctypes.c_double), ("r_max", ctypes.c_double)]
+
+
+class ups_pose(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3)]
+
+
+class ups_normal_params(ctypes.Structure):
+    _fields_ = [("atrous_levels", ctypes.c_int32), ("sigma_n", ctypes.c_float), ("sigma_r", ctypes.c_float),
+                ("max_rel_jump", ctypes.c_float)]
+
+
+class ups_icp_params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("d_max", ctypes.c_float * 4),
+                ("cos_theta_max", ctypes.c_float), ("stop_update_norm", ctypes.c_double),
+                ("min_inliers", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class ups_icp_result(ctypes.Structure):
+    _fields_ = [("T", ups_pose), ("rms", ctypes.c_double), ("trunc_cost", ctypes.c_double),
+                ("inlier_ratio", ctypes.c_double), ("inliers", ctypes.c_int64), ("valid", ctypes.c_int64),
+                ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("JtJ", ctypes.c_double * 21),
+                ("Jtr", ctypes.c_double * 6), ("last_update_norm", ctypes.c_double)]
+
+
+class ups_normal_eq(ctypes.Structure):
+    _fields_ = [("JtJ", ctypes.c_double * 21), ("Jtr", ctypes.c_double * 6), ("sum_r2", ctypes.c_double),
+                ("inliers", ctypes.c_int64), ("valid", ctypes.c_int64)]
+
+
+class ups_fuse_params(ctypes.Structure):
+    _fields_ = [("d_max", ctypes.c_float), ("cos_theta_max", ctypes.c_float),
+                ("min_cos_incidence", ctypes.c_float), ("max_count", ctypes.c_int32)]
+
+
+RESULT_BYTES = ctypes.sizeof(ups_icp_result)
+NEQ_BYTES = ctypes.sizeof(ups_normal_eq)
+
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load the built library (``python -m paper_2101_00585_amd.build``)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_SO):
+        raise UpsError(f"{_SO} is not built: run `python -m paper_2101_00585_amd.build`")
+    lib = ctypes.CDLL(_SO)
+    sig = {
+        "ups_context_create": [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64],
+        "ups_panorama_normals": [_P, _P, _P, _P, _P, _P],
+        "ups_pyramid_level": [_P, _P, _P, ctypes.c_int32, _P, _P],
+        "ups_register_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
+        "ups_fuse_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
+        "ups_correspondences": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
+        "ups_normal_equations": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P, _P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.ups_context_destroy.argtypes = [_P]
+    lib.ups_context_destroy.restype = None
+    lib.ups_last_error.argtypes = []
+    lib.ups_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = _LIB.ups_last_error().decode()
+        raise UpsError(f"upslam error {rc}: {msg}")
+
+
+# ----------------------------------------------------------------------------
+# parameters
+# ----------------------------------------------------------------------------
+
+@dataclass
+class NormalParams:
+    atrous_levels: int = 2
+    sigma_n: float = 0.5
+    sigma_r: float = 0.05
+    max_rel_jump: float = 0.5
+
+    def c(self):
+        return ups_normal_params(self.atrous_levels, self.sigma_n, self.sigma_r, self.max_rel_jump)
+
+
+@dataclass
+class IcpParams:
+    levels: int = 1
+    iters: tuple = (20, 0, 0, 0)
+    d_max: tuple = (0.5, 1.0, 2.0, 4.0)
+    cos_theta_max: float = math.cos(math.radians(30.0))
+    stop_update_norm: float = 0.0
+    min_inliers: int = 64
+    precision: int = PREC_KAHAN_F64
+
+    def c(self):
+        it = list(self.iters) + [0] * (4 - len(self.iters))
+        dm = list(self.d_max) + [self.d_max[-1]] * (4 - len(self.d_max))
+        return ups_icp_params(self.levels, (ctypes.c_int32 * 4)(*it), (ctypes.c_float * 4)(*dm),
+                              self.cos_theta_max, self.stop_update_norm, self.min_inliers, self.precision)
+
+
+@dataclass
+class FuseParams:
+    d_max: float = 0.2
+    cos_theta_max: float = math.cos(math.radians(30.0))
+    min_cos_incidence: float = 0.1
+    max_count: int = 10
+
+    def c(self):
+        return ups_fuse_params(self.d_max, self.cos_theta_max, self.min_cos_incidence, self.max_count)
+
+
+def geom_c(g) -> ups_geom:
+    """Any object with rows, cols, el_top, d_el, r_min, r_max."""
+    return ups_geom(int(g.rows), int(g.cols), float(g.el_top), float(g.d_el), float(g.r_min), float(g.r_max))
+
+
+# ----------------------------------------------------------------------------
+# torch plumbing
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _P(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, dtype, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise UpsError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise UpsError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise UpsError(f"{what} must be contiguous")
+    return _P(t.data_ptr())
+
+
+def pose_tensor(T, device="cuda"):
+    """Device FP64 pose (ups_pose layout: R row-major then t) from a 4x4."""
+    torch = _torch()
+    T = np.asarray(T, dtype=np.float64)
+    flat = np.concatenate([T[:3, :3].reshape(9), T[:3, 3]])
+    return torch.tensor(flat, dtype=torch.float64, device=device)
+
+
+def pose_from_tensor(t) -> np.ndarray:
+    p = t.detach().cpu().numpy().astype(np.float64)
+    T = np.eye(4)
+    T[:3, :3] = p[:9].reshape(3, 3)
+    T[:3, 3] = p[9:12]
+    return T
+
+
+class Context:
+    """A library context: device scratch for panoramas up to ``max_pixels``
+    pixels and batches of ``max_batch`` registrations totalling
+    ``max_batch_pixels`` pixels."""
+
+    def __init__(self, device: int = 0, max_pixels: int = 1 << 20, max_batch: int = 0, max_batch_pixels: int = 0):
+        lib = load()
+        h = _P()
+        _check(lib.ups_context_create(ctypes.byref(h), int(device), int(max_pixels), int(max_batch),
+                                      int(max_batch_pixels)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _LIB.ups_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def new_result(device="cuda"):
+    torch = _torch()
+    return torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_result(res) -> dict:
+    raw = bytes(res.detach().cpu().numpy().tobytes())
+    r = ups_icp_result.from_buffer_copy(raw)
+    T = np.eye(4)
+    T[:3, :3] = np.array(r.T.R[:]).reshape(3, 3)
+    T[:3, 3] = np.array(r.T.t[:])
+    return dict(T=T, rms=r.rms, trunc_cost=r.trunc_cost, inlier_ratio=r.inlier_ratio, inliers=r.inliers,
+                valid=r.valid, iters_run=r.iters_run, status=r.status, JtJ=np.array(r.JtJ[:]),
+                Jtr=np.array(r.Jtr[:]), last_update_norm=r.last_update_norm)
+
+
+def read_neq(t) -> dict:
+    r = ups_normal_eq.from_buffer_copy(bytes(t.detach().cpu().numpy().tobytes()))
+    return dict(JtJ=np.array(r.JtJ[:]), Jtr=np.array(r.Jtr[:]), sum_r2=r.sum_r2, inliers=r.inliers, valid=r.valid)
+
+
+# ----------------------------------------------------------------------------
+# entry points (same names as the C ABI without the ups_ prefix)
+# ----------------------------------------------------------------------------
+
+def panorama_normals(ctx: Context, geom, depth, surfel=None, params: NormalParams | None = None):
+    torch = _torch()
+    p = (params or NormalParams()).c()
+    if surfel is None:
+        surfel = torch.empty((geom.rows, geom.cols, 4), dtype=torch.float32, device=depth.device)
+    g = geom_c(geom)
+    _check(_LIB.ups_panorama_normals(ctx.handle, ctypes.byref(g), _dev_ptr(depth, torch.float32, "depth"),
+                                     _dev_ptr(surfel, torch.float32, "surfel"), ctypes.byref(p), _stream()))
+    return surfel
+
+
+def pyramid_level(ctx: Context, geom, surfel, level: int, out=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty((geom.rows >> level, geom.cols >> level, 4), dtype=torch.float32, device=surfel.device)
+    g = geom_c(geom)
+    _check(_LIB.ups_pyramid_level(ctx.handle, ctypes.byref(g), _dev_ptr(surfel, torch.float32, "surfel"),
+                                  int(level), _dev_ptr(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def register_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, init, params: IcpParams | None = None,
+                  result=None):
+    """``init``: a 4x4 (host) or a device FP64 pose tensor.  Returns the device
+    result buffer (``read_result`` decodes it)."""
+    torch = _torch()
+    p = (params or IcpParams()).c()
+    if result is None:
+        result = new_result(scan_surfel.device)
+    if isinstance(init, torch.Tensor):
+        init_t = init
+    else:
+        init_t = pose_tensor(init, scan_surfel.device)
+    sg, kg = geom_c(scan_geom), geom_c(kf_geom)
+    _check(_LIB.ups_register_scan(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan surfel"),
+                                  ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"),
+                                  _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
+                                  _dev_ptr(result, torch.uint8, "result"), _stream()))
+    result._keep_init = init_t  # keep a host-made init alive until the stream consumes it
+    return result
+
+
+def result_pose(result):
+    """Device view of the pose inside a result buffer (for fuse_scan)."""
+    return result[: ctypes.sizeof(ups_pose)].view(_torch().float64)
+
+
+def fuse_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, kf_count, T, params: FuseParams | None = None):
+    torch = _torch()
+    p = (params or FuseParams()).c()
+    T_t = T if isinstance(T, torch.Tensor) else pose_tensor(T, scan_surfel.device)
+    sg, kg = geom_c(scan_geom), geom_c(kf_geom)
+    _check(_LIB.ups_fuse_scan(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan surfel"),
+                              ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"),
+                              _dev_ptr(kf_count, torch.int16, "keyframe count") if kf_count.dtype == torch.int16
+                              else _dev_ptr(kf_count, torch.uint16, "keyframe count"),
+                              _dev_ptr(T_t, torch.float64, "pose"), ctypes.byref(p), _stream()))
+    return kf_surfel, kf_count
+
+
+def correspondences(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T, d_max=0.5,
+                    cos_theta_max=math.cos(math.radians(30.0))):
+    torch = _torch()
+    dev = scan_surfel.device
+    T_t = T if isinstance(T, torch.Tensor) else pose_tensor(T, dev)
+    idx = torch.empty((scan_geom.rows, scan_geom.cols), dtype=torch.int32, device=dev)
+    inl = torch.empty((scan_geom.rows, scan_geom.cols), dtype=torch.uint8, device=dev)
+    sg, kg = geom_c(scan_geom), geom_c(kf_geom)
+    _check(_LIB.ups_correspondences(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan"),
+                                    ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe"),
+                                    _dev_ptr(T_t, torch.float64, "pose"), float(d_max), float(cos_theta_max),
+                                    _dev_ptr(idx, torch.int32, "kf_index"), _dev_ptr(inl, torch.uint8, "inlier"),
+                                    _stream()))
+    idx._keep = T_t
+    return idx, inl
+
+
+def normal_equations(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T, d_max=0.5,
+                     cos_theta_max=math.cos(math.radians(30.0)), precision=PREC_KAHAN_F64):
+    torch = _torch()
+    dev = scan_surfel.device
+    T_t = T if isinstance(T, torch.Tensor) else pose_tensor(T, dev)
+    out = torch.zeros(NEQ_BYTES, dtype=torch.uint8, device=dev)
+    sg, kg = geom_c(scan_geom), geom_c(kf_geom)
+    _check(_LIB.ups_normal_equations(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan"),
+                                     ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe"),
+                                     _dev_ptr(T_t, torch.float64, "pose"), float(d_max), float(cos_theta_max),
+                                     int(precision), _dev_ptr(out, torch.uint8, "out"), _stream()))
+    out._keep = T_t
+    return out

@@ -1,0 +1,50 @@
+// Registration descriptors shared by the single and batched ICP launchers.
+#pragma once
+
+#include "ups_internal.hpp"
+
+namespace ups {
+
+enum { MODE_ITER = 0, MODE_EVAL = 1 };
+
+// Registration state, two ping-pong slots per registration.
+struct RegState {
+    double R[9], t[3];  // current pose (scan -> keyframe)
+    double last_norm;   // |xi| of the last applied update
+    int iters_run;      // applied updates
+    int status;         // UPS_CONVERGED / UPS_MAX_ITERS / UPS_DEGENERATE / UPS_NO_INLIERS
+    int stop;           // the registration stopped (degenerate / too few inliers)
+    int level_active;   // 0 once the current level met its stop criterion
+    int pending;        // the partials of the previous launch await their update
+    int npartials;      // number of those partials
+};
+
+// One registration as the kernels see it.
+struct Inst {
+    DGeom sg[4], kg[4];           // geometry of each pyramid level
+    const float4 *scan[4], *kf[4];  // surfel images of each level (level 0 = caller's)
+    RegState *state;              // [2]
+    double *partials;             // [2][pstride][kPartialStride]
+    int pstride;
+    int nblocks[4];               // blocks (tiles) per level
+    ups_icp_result *res;          // finish target (or null)
+    ups_normal_eq *neq;           // finish target (or null)
+};
+
+// Per-launch arguments.
+struct StepArgs {
+    int level, parity, first_of_level, check_max_iters;
+    float d_max2, cos_theta, tau2;
+    int min_inliers;
+    double stop_norm;
+};
+
+int pick_k_single(int npix);
+ups_status launch_register(const Inst &I, const ups_pose *init, const ups_icp_params &p, hipStream_t s);
+ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_theta, int precision,
+                       hipStream_t s);
+ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
+                            const StepArgs &a, int blocks, hipStream_t s);
+ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, hipStream_t s);
+
+}  // namespace ups

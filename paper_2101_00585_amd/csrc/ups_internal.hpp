@@ -1,0 +1,87 @@
+// Host-side internals of the library: the context (all device scratch memory,
+// allocated once), error reporting, geometry validation and the per-geometry
+// ray-table cache, plus the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ups_device.hpp"
+#include "upslam.h"
+
+namespace ups {
+
+void set_error(const std::string &msg);
+
+#define UPS_CHECK_HIP(expr)                                                                   \
+    do {                                                                                      \
+        hipError_t _e = (expr);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            ::ups::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));              \
+            return UPS_ERR_HIP;                                                               \
+        }                                                                                     \
+    } while (0)
+
+#define UPS_REQUIRE(cond, msg)                                                                \
+    do {                                                                                      \
+        if (!(cond)) {                                                                        \
+            ::ups::set_error(msg);                                                            \
+            return UPS_ERR_INVALID_ARG;                                                       \
+        }                                                                                     \
+    } while (0)
+
+struct LutEntry {
+    int rows, cols;
+    double el_top, d_el;
+    float2 *row, *col;  // device
+};
+
+struct RegState;
+
+}  // namespace ups
+
+struct ups_context {
+    int device = 0;
+    int64_t max_pixels = 0;
+    int32_t max_batch = 0;
+    int64_t max_batch_pixels = 0;
+    // scratch
+    float4 *pyr_scan = nullptr;  // levels 1..3 of a scan, max_pixels * 21/64
+    float4 *pyr_kf = nullptr;
+    float4 *tmp_surfel = nullptr;  // a-trous ping-pong, max_pixels
+    unsigned long long *fill_key = nullptr;  // fuse fill pass, max_pixels
+    double *partials = nullptr;              // [2][max_partial_blocks][kPartialStride] block partials
+    int64_t max_partial_blocks = 0;
+    ups::RegState *state = nullptr;          // [2] registration state slots
+    // ray tables
+    float2 *lut_arena = nullptr;
+    size_t lut_capacity = 0, lut_used = 0;  // in float2
+    std::vector<ups::LutEntry> luts;
+    std::mutex mu;
+};
+
+namespace ups {
+
+constexpr int kPartialStride = 32;  // doubles per block partial
+
+// Validate a geometry and return its device view at pyramid level `level`
+// (ray tables are uploaded on first use of the geometry).
+ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream_t stream, DGeom *out);
+ups_status check_ptr(const void *p, size_t align, const char *what);
+
+// launchers (each returns UPS_OK or sets the error)
+ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, float4 *surfel,
+                          const ups_normal_params &p, hipStream_t s);
+ups_status launch_subsample(const DGeom &g0, const float4 *src, int level, float4 *dst, hipStream_t s);
+ups_status launch_correspondences(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
+                                  const ups_pose *T, float d_max, float cos_theta, int32_t *idx, uint8_t *inl,
+                                  hipStream_t s);
+ups_status launch_fuse(ups_context *ctx, const DGeom &sg, const float4 *scan, const DGeom &kg, float4 *kf,
+                       uint16_t *count, const ups_pose *T, const ups_fuse_params &p, hipStream_t s);
+
+}  // namespace ups

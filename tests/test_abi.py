@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI (no GPU): the built library loads and exports
+every function that include/upslam.h declares, and the Python structs have
+the header's sizes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "upslam.h")
+SO = os.path.join(ROOT, "paper_2101_00585_amd", "libupslam.so")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ups_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(SO):
+        from paper_2101_00585_amd import build
+        build.build()
+    return ctypes.CDLL(SO)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "ups_register_scan" in names and "ups_fuse_scan" in names and "ups_panorama_normals" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_header():
+    import paper_2101_00585_amd as ups
+    # ups_pose: 12 doubles; ups_geom: 2 ints + 4 doubles; result layout fixed by the header
+    assert ctypes.sizeof(ups.ups_pose) == 96
+    assert ctypes.sizeof(ups.ups_geom) == 40
+    assert ctypes.sizeof(ups.ups_icp_params) == 4 + 16 + 16 + 4 + 8 + 4 + 4
+    assert ups.RESULT_BYTES == 96 + 24 + 16 + 8 + 21 * 8 + 6 * 8 + 8
+    assert ups.NEQ_BYTES == 21 * 8 + 6 * 8 + 8 + 16
+
+
+def test_last_error_without_gpu(lib):
+    lib.ups_last_error.restype = ctypes.c_char_p
+    assert isinstance(lib.ups_last_error(), bytes)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    """Null context / pointers are rejected before any device work."""
+    import paper_2101_00585_amd as ups
+    L = ups.load()
+    g = ups.ups_geom(64, 512, 0.3, 0.01, 0.0, 50.0)
+    p = ups.IcpParams().c()
+    rc = L.ups_register_scan(None, ctypes.byref(g), None, ctypes.byref(g), None, None, ctypes.byref(p), None, None)
+    assert rc == -1
+    np_ = ups.NormalParams().c()
+    rc = L.ups_panorama_normals(None, ctypes.byref(g), None, None, ctypes.byref(np_), None)
+    assert rc == -1
+    out = ctypes.c_void_p()
+    rc = L.ups_context_create(ctypes.byref(out), 0, 10, 0, 0)
+    assert rc == -1 and not out.value
