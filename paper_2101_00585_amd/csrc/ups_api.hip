@@ -134,10 +134,12 @@ ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels,
     if (e == hipSuccess) e = hipMalloc(&c->pyr_kf, pyr * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(&c->tmp_surfel, max_pixels * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(&c->fill_key, max_pixels * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(c->fill_key, 0xFF, max_pixels * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&c->partials, 2 * c->max_partial_blocks * kPartialStride * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&c->state, 2 * sizeof(RegState));
     if (e == hipSuccess) e = hipMemset(c->state, 0, 2 * sizeof(RegState));
     if (e == hipSuccess) e = hipMalloc(&c->lut_arena, c->lut_capacity * sizeof(float2));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         set_error(std::string("context allocation failed: ") + hipGetErrorString(e));
         ups_context_destroy(c);

@@ -1,17 +1,19 @@
 // Keyframe update (UPSLAM Section III-C) on gfx950.
 //
-//   k_fuse_update  one thread per keyframe pixel: pixels holding samples are
-//                  mapped back into the sweep (T^-1), gated by the similarity
-//                  filter and averaged with weights count : 1; empty pixels get
-//                  their fill key reset.
-//   k_fuse_fill    one thread per sweep pixel: valid surfels are projected into
-//                  the keyframe and compete for empty pixels with a 64-bit
-//                  atomicMin on (FP32 bits of |q|, sweep index) -- the nearest
-//                  surface wins, ties broken by the smaller index.
-//   k_fuse_resolve one thread per keyframe pixel: winners are written with
-//                  count 1.
-// The three passes touch disjoint keyframe pixels (count > 0 vs count == 0 at
-// entry), so their order only matters through the fill keys.
+//   k_fuse_update_fill  one launch, two kinds of blocks:
+//     update blocks, one thread per keyframe pixel: pixels holding samples
+//       are mapped back into the sweep (T^-1), gated by the similarity filter
+//       and averaged with weights count : 1;
+//     fill blocks, one thread per sweep pixel: valid surfels are projected
+//       into the keyframe and compete for its empty pixels with a 64-bit
+//       atomicMin on (FP32 bits of |q|, sweep index) -- the nearest surface
+//       wins, ties broken by the smaller index.
+//   k_fuse_resolve  one thread per keyframe pixel: winners are written with
+//     count 1 and their fill key is reset.
+// Update and fill touch disjoint keyframe pixels (count > 0 vs count == 0 at
+// entry; an update keeps count > 0), so they can run in the same launch.  The
+// fill keys are all-ones between calls: set at context creation, restored by
+// the resolve pass.
 #include "ups_internal.hpp"
 
 namespace ups {
@@ -29,17 +31,13 @@ struct FuseArgs {
 
 constexpr unsigned long long kNoKey = ~0ull;
 
-__global__ __launch_bounds__(kBlock) void k_fuse_update(FuseArgs a) {
+__device__ __forceinline__ void fuse_update(const FuseArgs &a, int px) {
     // no FMA contraction: a sample at the pixel's own point must give r_new = r
 #pragma clang fp contract(off)
     const int npix = a.kg.rows * a.kg.cols;
-    const int px = blockIdx.x * kBlock + threadIdx.x;
     if (px >= npix) return;
     const int c = a.count[px];
-    if (c == 0) {
-        a.key[px] = kNoKey;
-        return;
-    }
+    if (c == 0) return;
     const float4 s1 = a.kf[px];
     if (!surfel_ok(a.kg, s1)) return;
     const Rt32 T = load_pose_f32(a.pose);
@@ -76,9 +74,8 @@ __global__ __launch_bounds__(kBlock) void k_fuse_update(FuseArgs a) {
     a.count[px] = (uint16_t)(c + 1 < a.max_count ? c + 1 : a.max_count);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fuse_fill(FuseArgs a) {
+__device__ __forceinline__ void fuse_fill(const FuseArgs &a, int p) {
     const int npix = a.sg.rows * a.sg.cols;
-    const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
     const float4 s2 = a.scan[p];
     if (!surfel_ok(a.sg, s2)) return;
@@ -96,6 +93,11 @@ __global__ __launch_bounds__(kBlock) void k_fuse_fill(FuseArgs a) {
     atomicMin(&a.key[kp], key);
 }
 
+__global__ __launch_bounds__(kBlock) void k_fuse_update_fill(FuseArgs a, int update_blocks) {
+    if ((int)blockIdx.x < update_blocks) fuse_update(a, blockIdx.x * kBlock + threadIdx.x);
+    else fuse_fill(a, (blockIdx.x - update_blocks) * kBlock + threadIdx.x);
+}
+
 __global__ __launch_bounds__(kBlock) void k_fuse_resolve(FuseArgs a) {
     const int npix = a.kg.rows * a.kg.cols;
     const int px = blockIdx.x * kBlock + threadIdx.x;
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_fuse_resolve(FuseArgs a) {
     if (a.count[px] != 0) return;
     const unsigned long long key = a.key[px];
     if (key == kNoKey) return;
+    a.key[px] = kNoKey;
     const int p = (int)(key & 0xffffffffu);
     const float rq = __uint_as_float((unsigned)(key >> 32));
     const Rt32 T = load_pose_f32(a.pose);
@@ -126,9 +129,8 @@ ups_status launch_fuse(ups_context *ctx, const DGeom &sg, const float4 *scan, co
     a.min_cos_inc = p.min_cos_incidence;
     a.max_count = p.max_count;
     const int nk = kg.rows * kg.cols, ns = sg.rows * sg.cols;
-    hipLaunchKernelGGL(k_fuse_update, dim3((nk + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
-    UPS_CHECK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_fuse_fill, dim3((ns + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+    const int ub = (nk + kBlock - 1) / kBlock, fb = (ns + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_fuse_update_fill, dim3(ub + fb), dim3(kBlock), 0, s, a, ub);
     UPS_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_fuse_resolve, dim3((nk + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
     UPS_CHECK_HIP(hipGetLastError());

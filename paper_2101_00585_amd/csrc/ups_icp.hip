@@ -88,11 +88,10 @@ __device__ __forceinline__ void block_reduce(Acc (&x)[NV], Acc (*rows)[16], Acc 
     __syncthreads();
 }
 
-// Reduce the first NV values of `n` block partials in a fixed order: thread t
-// takes partials t, t+256, ...; then block_reduce.
+// Load this thread's share of `n` block partials (partials t, t+256, ... for
+// thread t) and add them up in that fixed order; block_reduce finishes.
 template <int NV, typename Acc>
-__device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (*rows)[16], Acc *tot) {
-    Acc x[NV];
+__device__ __forceinline__ void load_partials(const double *part, int n, Acc (&x)[NV]) {
 #pragma unroll
     for (int v = 0; v < NV; v++) x[v] = 0;
     for (int b = threadIdx.x; b < n; b += kBlock) {
@@ -100,6 +99,12 @@ __device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (
 #pragma unroll
         for (int v = 0; v < NV; v++) x[v] += (Acc)pb[v];
     }
+}
+
+template <int NV, typename Acc>
+__device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (*rows)[16], Acc *tot) {
+    Acc x[NV];
+    load_partials<NV, Acc>(part, n, x);
     block_reduce<NV, Acc>(x, rows, tot);
 }
 
@@ -107,7 +112,7 @@ __device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (
 
 template <typename T>
 __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
-    T A[6][6], L[6][6];
+    T A[6][6], L[6][6], inv[6];
     int e = 0;
     for (int a = 0; a < 6; a++)
         for (int c = a; c < 6; c++) {
@@ -123,37 +128,50 @@ __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
         for (int k = 0; k < c; k++) d -= L[c][k] * L[c][k];
         if (!(d > T(1e-12) * maxd)) return UPS_DEGENERATE;
         L[c][c] = sqrt(d);
+        inv[c] = T(1) / L[c][c];
         for (int r = c + 1; r < 6; r++) {
             T s = A[r][c];
             for (int k = 0; k < c; k++) s -= L[r][k] * L[c][k];
-            L[r][c] = s / L[c][c];
+            L[r][c] = s * inv[c];
         }
     }
     T y[6];
     for (int r = 0; r < 6; r++) {
         T s = -b[r];
         for (int k = 0; k < r; k++) s -= L[r][k] * y[k];
-        y[r] = s / L[r][r];
+        y[r] = s * inv[r];
     }
     for (int r = 5; r >= 0; r--) {
         T s = y[r];
         for (int k = r + 1; k < 6; k++) s -= L[k][r] * xi[k];
-        xi[r] = s / L[r][r];
+        xi[r] = s * inv[r];
     }
     return UPS_CONVERGED;
 }
 
 // R, t <- Exp(xi) (R, t) with xi = (omega, v): Rodrigues rotation and the V
-// matrix, series coefficients below |omega| = 1e-4.
+// matrix.  Below |omega| = 1/4 the three coefficients sin(th)/th,
+// (1-cos th)/th^2 and (th-sin th)/th^3 come from their Taylor series to the
+// th^14 term (remainder < 1e-20), which avoids the cancellation of the closed
+// forms and any sin/cos; above it the closed forms are used.
 template <typename T>
 __device__ void exp_compose(const T *xi, double *R, double *t) {
     const T w0 = xi[0], w1 = xi[1], w2 = xi[2];
     const T th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
     T A, B, C;
-    if (th < T(1e-4)) {
-        A = T(1) - th2 / T(6) + th2 * th2 / T(120);
-        B = T(0.5) - th2 / T(24) + th2 * th2 / T(720);
-        C = T(1) / T(6) - th2 / T(120) + th2 * th2 / T(5040);
+    if (th < T(0.25)) {
+        // 1/n! for n = 1..17
+        constexpr double f[18] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040,
+                                  1.0 / 40320, 1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600,
+                                  1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0,
+                                  1.0 / 20922789888000.0, 1.0 / 355687428096000.0};
+        A = B = C = 0;
+        for (int k = 7; k >= 0; k--) {
+            const T sg = (k & 1) ? T(-1) : T(1);
+            A = A * th2 + sg * (T)f[2 * k + 1];
+            B = B * th2 + sg * (T)f[2 * k + 2];
+            C = C * th2 + sg * (T)f[2 * k + 3];
+        }
     } else {
         A = sin(th) / th;
         B = (T(1) - cos(th)) / th2;
@@ -203,6 +221,10 @@ __device__ void gn_step(const StepArgs &a, const T *tot, RegState &S) {
 
 // ------------------------------------------------------------------ kernel
 
+// Partials a launch over `nblocks` blocks leaves for its successor: one per
+// block, or a single folded one when there are more than 256.
+__device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
+
 template <int K, int PREC, int MODE>
 __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
     constexpr int NV = (MODE == MODE_ITER) ? 29 : 31;  // EVAL adds valid count and truncated cost
@@ -218,12 +240,28 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     __shared__ Acc rows[31][16];
     __shared__ Acc tot[32];
     __shared__ int active;
+    const DGeom sg = I.sg[l], kg = I.kg[l];
+    const float4 *__restrict__ scan = I.scan[l];
+    const float4 *__restrict__ kf = I.kf[l];
+    const int npix = sg.rows * sg.cols;
+    const int base = tile * (kBlock * K);
+
+    // ---- issue the independent loads together: this launch's scan surfels,
+    // the previous launch's block partials and the state
+    float4 s2[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int p = base + k * kBlock + tid;
+        s2[k] = p < npix ? scan[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    Acc px[29];
+    load_partials<29, Acc>(part_in, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0, px);
     if (tid == 0) S = *slot_in;
     __syncthreads();
 
     // ---- 0. the previous launch's update, solved identically by every block
     if (S.pending && !S.stop) {
-        reduce_partials<29, Acc>(part_in, S.npartials, rows, tot);
+        block_reduce<29, Acc>(px, rows, tot);
         if (tid == 0) gn_step<Acc>(a, tot, S);
     }
     if (tid == 0) {
@@ -244,21 +282,9 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     for (int k = 0; k < 9; k++) T.r[k] = (float)S.R[k];
 #pragma unroll
     for (int k = 0; k < 3; k++) T.t[k] = (float)S.t[k];
-    const DGeom sg = I.sg[l], kg = I.kg[l];
-    const float4 *__restrict__ scan = I.scan[l];
-    const float4 *__restrict__ kf = I.kf[l];
-    const int npix = sg.rows * sg.cols;
-
     float s[NV], c[NV];
 #pragma unroll
     for (int v = 0; v < NV; v++) s[v] = c[v] = 0.f;
-    const int base = tile * (kBlock * K);
-    float4 s2[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int p = base + k * kBlock + tid;
-        s2[k] = p < npix ? scan[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
 #pragma unroll
     for (int k = 0; k < K; k++) {
         // the 64 pixels of a wavefront lie in one row (cols is a multiple of 64)
@@ -342,7 +368,8 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity) {
     __shared__ Acc rows[31][16];
     __shared__ Acc tot[32];
     const RegState *S = I.state + parity;
-    reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, S->npartials, rows, tot);
+    reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, npartials_of(I.nblocks[0]),
+                             rows, tot);
     if (threadIdx.x != 0) return;
     const double n_in = (double)tot[28], n_valid = (double)tot[29];
     if (I.res) {
@@ -573,6 +600,7 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
     a.stop_norm = p.stop_update_norm;
     int parity = 0;
     ups_status st;
+    a.prev_level = -1;
     for (int l = p.levels - 1; l >= 0; l--) {
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
@@ -580,6 +608,7 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
             a.parity = parity;
             a.first_of_level = it == 0;
             if ((st = launch_one(Ks[l], p.precision, MODE_ITER, I, a, I.nblocks[l], s)) != UPS_OK) return st;
+            a.prev_level = l;
             parity ^= 1;
             if (I.nblocks[l] > 256 && (st = launch_collapse_one(p.precision, MODE_ITER, I, parity, s)) != UPS_OK)
                 return st;
@@ -611,6 +640,7 @@ ups_status launch_eval(const Inst &I0, const ups_pose *T, float d_max, float cos
     memset(&a, 0, sizeof(a));
     a.level = 0;
     a.parity = 0;
+    a.prev_level = -1;
     a.d_max2 = d_max * d_max;
     a.tau2 = a.d_max2;
     a.cos_theta = cos_theta;

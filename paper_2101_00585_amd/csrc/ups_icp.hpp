@@ -34,6 +34,7 @@ struct Inst {
 // Per-launch arguments.
 struct StepArgs {
     int level, parity, first_of_level, check_max_iters;
+    int prev_level;  // level of the previous launch (-1: none), whose partials this launch reduces
     float d_max2, cos_theta, tau2;
     int min_inliers;
     double stop_norm;

@@ -5,9 +5,30 @@
 
 namespace ups {
 
-// One thread per pixel.  The right neighbour wraps in azimuth; the lower
-// neighbour is the previous row on the last row.  Rows of a wavefront share
-// cache lines, so the neighbour reads are served from L1/L2.
+// Raw normal of pixel (i, j) from its range rc and the ranges of its right
+// neighbour (i, j+1 mod cols) and lower neighbour (i+1, j) -- (i-1, j) on the
+// last row: the normalised cross product of the two difference vectors,
+// oriented towards the sensor; zero when a range is invalid, a neighbour jumps
+// by more than max_rel_jump * rc, or the cross product is degenerate.
+__device__ __forceinline__ float3 raw_normal(const DGeom &g, int i, int j, int ib, float rc, float ra, float rb,
+                                             float max_rel_jump) {
+    float3 o = make_float3(0.f, 0.f, 0.f);
+    if (!(range_ok(g, rc) && ib >= 0 && range_ok(g, ra) && range_ok(g, rb))) return o;
+    if (fabsf(ra - rc) > max_rel_jump * rc || fabsf(rb - rc) > max_rel_jump * rc) return o;
+    const int ja = (j + 1 == g.cols) ? 0 : j + 1;
+    const float3 uc = ray(g, i, j), ua = ray(g, i, ja), ub = ray(g, ib, j);
+    const float3 pc = make_float3(rc * uc.x, rc * uc.y, rc * uc.z);
+    const float3 a = make_float3(ra * ua.x - pc.x, ra * ua.y - pc.y, ra * ua.z - pc.z);
+    const float3 b = make_float3(rb * ub.x - pc.x, rb * ub.y - pc.y, rb * ub.z - pc.z);
+    const float3 n = cross3(a, b);
+    const float nn = sqrtf(dot3(n, n));
+    if (!(nn > 1e-6f * sqrtf(dot3(a, a)) * sqrtf(dot3(b, b)))) return o;
+    const float s = (dot3(n, pc) > 0.f) ? -1.f / nn : 1.f / nn;
+    return make_float3(n.x * s, n.y * s, n.z * s);
+}
+
+// Raw normals only (no smoothing): one thread per pixel; the neighbour reads
+// are served from L1/L2.
 __global__ __launch_bounds__(kBlock) void k_normals_raw(DGeom g, const float *__restrict__ depth,
                                                         float4 *__restrict__ out, float max_rel_jump) {
     const int npix = g.rows * g.cols;
@@ -15,36 +36,56 @@ __global__ __launch_bounds__(kBlock) void k_normals_raw(DGeom g, const float *__
     if (p >= npix) return;
     const int i = p / g.cols, j = p - i * g.cols;
     const float rc = depth[p];
-    float4 o = make_float4(0.f, 0.f, 0.f, range_ok(g, rc) ? rc : 0.f);
     const int ja = (j + 1 == g.cols) ? 0 : j + 1;
     const int ib = (i + 1 < g.rows) ? i + 1 : i - 1;
-    if (range_ok(g, rc) && ib >= 0) {
-        const float ra = depth[i * g.cols + ja], rb = depth[ib * g.cols + j];
-        if (range_ok(g, ra) && range_ok(g, rb) && !(fabsf(ra - rc) > max_rel_jump * rc) &&
-            !(fabsf(rb - rc) > max_rel_jump * rc)) {
-            const float3 uc = ray(g, i, j), ua = ray(g, i, ja), ub = ray(g, ib, j);
-            const float3 pc = make_float3(rc * uc.x, rc * uc.y, rc * uc.z);
-            const float3 a = make_float3(ra * ua.x - pc.x, ra * ua.y - pc.y, ra * ua.z - pc.z);
-            const float3 b = make_float3(rb * ub.x - pc.x, rb * ub.y - pc.y, rb * ub.z - pc.z);
-            const float3 n = cross3(a, b);
-            const float nn = sqrtf(dot3(n, n));
-            if (nn > 1e-6f * sqrtf(dot3(a, a)) * sqrtf(dot3(b, b))) {
-                const float s = (dot3(n, pc) > 0.f) ? -1.f / nn : 1.f / nn;
-                o.x = n.x * s;
-                o.y = n.y * s;
-                o.z = n.z * s;
-            }
-        }
-    }
-    out[p] = o;
+    const float ra = depth[i * g.cols + ja], rb = ib >= 0 ? depth[ib * g.cols + j] : 0.f;
+    const float3 n = raw_normal(g, i, j, ib, rc, ra, rb, max_rel_jump);
+    out[p] = make_float4(n.x, n.y, n.z, range_ok(g, rc) ? rc : 0.f);
 }
 
-constexpr int kTileW = 64, kTileH = 16;
+constexpr int kTileW = 64, kTileH = 4;
 
-// One a-trous level with taps spaced `step`: the block stages a
-// (16 + 4 step) x (64 + 4 step) surfel tile (rows outside the image marked
-// empty, columns wrapped) in LDS, then each thread filters 4 pixels of one
-// column.  All edge-stopping factors of a tap share one exponential.
+// One a-trous output from an LDS surfel tile of row pitch LW whose pixel
+// (ly, lx) is the output (ly + 2 step, lx + 2 step) of the tile: 5x5 B3-spline
+// taps spaced `step`, only taps with a normal, weight
+// h[dy] h[dx] exp(-(dr^2 + (2 - 2 n_p.n_q)/sigma_n^2)) with
+// dr = (r_q - r_p)/(sigma_r r_p), renormalised; the range is unchanged.
+__device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int ly, int lx, int step,
+                                                 float inv_sigma_r, float inv_sigma_n2) {
+    const float h[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+    const float4 c = tile[(ly + 2 * step) * LW + lx + 2 * step];
+    float4 o = make_float4(0.f, 0.f, 0.f, c.w);
+    if (!normal_ok(c)) return o;
+    const float inv_rp = inv_sigma_r / c.w;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 5; dy++) {
+        const float4 *row = tile + (ly + dy * step) * LW + lx;
+#pragma unroll
+        for (int dx = 0; dx < 5; dx++) {
+            const float4 q = row[dx * step];
+            if (!normal_ok(q)) continue;
+            const float dr = (q.w - c.w) * inv_rp;
+            const float dn = 2.f - 2.f * (c.x * q.x + c.y * q.y + c.z * q.z);
+            const float w = h[dy] * h[dx] * __expf(-(dr * dr + dn * inv_sigma_n2));
+            ax += w * q.x;
+            ay += w * q.y;
+            az += w * q.z;
+        }
+    }
+    const float nn = sqrtf(ax * ax + ay * ay + az * az);
+    if (nn > 0.f) {
+        const float s = 1.f / nn;
+        o.x = ax * s;
+        o.y = ay * s;
+        o.z = az * s;
+    }
+    return o;
+}
+
+// One a-trous level with taps spaced `step`: the block stages the
+// (4 + 4 step) x (64 + 4 step) surfel tile around its 4 x 64 outputs in LDS
+// (rows outside the image empty, columns wrapped), one output per thread.
 __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__restrict__ in, float4 *__restrict__ out,
                                                    int step, float inv_sigma_r, float inv_sigma_n2) {
     extern __shared__ float4 tile[];
@@ -61,63 +102,81 @@ __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__rest
         tile[idx] = v;
     }
     __syncthreads();
-    const float h[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
     const int tx = threadIdx.x & (kTileW - 1), ty = threadIdx.x / kTileW;
-#pragma unroll
-    for (int k = 0; k < kTileH / (kBlock / kTileW); k++) {
-        const int ly = ty + k * (kBlock / kTileW);
-        const int gy = y0 + ly;
-        if (gy >= g.rows) break;
-        const float4 c = tile[(ly + halo) * LW + tx + halo];
-        float4 o = make_float4(0.f, 0.f, 0.f, c.w);
-        if (normal_ok(c)) {
-            const float inv_rp = inv_sigma_r / c.w;
-            float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-            for (int dy = 0; dy < 5; dy++) {
-                const float4 *row = tile + (ly + dy * step) * LW + tx;
-#pragma unroll
-                for (int dx = 0; dx < 5; dx++) {
-                    const float4 q = row[dx * step];
-                    if (!normal_ok(q)) continue;
-                    const float dr = (q.w - c.w) * inv_rp;
-                    const float dn = 2.f - 2.f * (c.x * q.x + c.y * q.y + c.z * q.z);
-                    const float w = h[dy] * h[dx] * __expf(-(dr * dr + dn * inv_sigma_n2));
-                    ax += w * q.x;
-                    ay += w * q.y;
-                    az += w * q.z;
-                }
-            }
-            const float nn = sqrtf(ax * ax + ay * ay + az * az);
-            if (nn > 0.f) {
-                const float s = 1.f / nn;
-                o.x = ax * s;
-                o.y = ay * s;
-                o.z = az * s;
-            }
-        }
-        out[gy * g.cols + x0 + tx] = o;
+    const int gy = y0 + ty;
+    if (gy >= g.rows) return;
+    out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, step, inv_sigma_r, inv_sigma_n2);
+}
+
+// Raw normals and the first a-trous level (step 1) in one pass: the block
+// stages the ranges of its 4 x 64 outputs plus a 2-pixel halo (and the
+// neighbour row/column the cross products need), computes the raw normals of
+// the 8 x 68 halo tile into LDS, then filters.
+constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
+constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
+
+__global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float *__restrict__ depth,
+                                                           float4 *__restrict__ out, float max_rel_jump,
+                                                           float inv_sigma_r, float inv_sigma_n2) {
+    __shared__ float rng[kDH][kDW];
+    __shared__ float4 raw[kFH * kFW];
+    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+    // ranges of rows y0-3 .. y0+kTileH+2 and columns x0-2 .. x0+kTileW+2
+    for (int idx = threadIdx.x; idx < kDH * kDW; idx += kBlock) {
+        const int ly = idx / kDW, lx = idx - ly * kDW;
+        const int gy = y0 - 3 + ly;
+        int gx = x0 - 2 + lx;
+        gx = gx < 0 ? gx + g.cols : (gx >= g.cols ? gx - g.cols : gx);
+        rng[ly][lx] = (gy >= 0 && gy < g.rows) ? depth[gy * g.cols + gx] : 0.f;
     }
+    __syncthreads();
+    // raw normals of rows y0-2 .. y0+kTileH+1, columns x0-2 .. x0+kTileW+1
+    for (int idx = threadIdx.x; idx < kFH * kFW; idx += kBlock) {
+        const int ly = idx / kFW, lx = idx - ly * kFW;
+        const int gy = y0 - 2 + ly;
+        int gx = x0 - 2 + lx;
+        gx = gx < 0 ? gx + g.cols : (gx >= g.cols ? gx - g.cols : gx);
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gy >= 0 && gy < g.rows) {
+            const int dy = ly + 1, dx = lx;  // this pixel in the range tile
+            const float rc = rng[dy][dx];
+            const int ib = (gy + 1 < g.rows) ? gy + 1 : gy - 1;
+            const float rb = (ib == gy + 1) ? rng[dy + 1][dx] : rng[dy - 1][dx];
+            const float3 n = raw_normal(g, gy, gx, ib, rc, rng[dy][dx + 1], rb, max_rel_jump);
+            v = make_float4(n.x, n.y, n.z, range_ok(g, rc) ? rc : 0.f);
+        }
+        raw[idx] = v;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & (kTileW - 1), ty = threadIdx.x / kTileW;
+    const int gy = y0 + ty;
+    if (gy >= g.rows) return;
+    out[gy * g.cols + x0 + tx] = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
 }
 
 ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, float4 *surfel,
                           const ups_normal_params &p, hipStream_t s) {
     const int npix = g.rows * g.cols;
     const int L = p.atrous_levels;
-    float4 *bufs[2] = {surfel, ctx->tmp_surfel};
+    const float inv_sr = 1.f / p.sigma_r, inv_sn2 = 1.f / (p.sigma_n * p.sigma_n);
+    if (L == 0) {
+        hipLaunchKernelGGL(k_normals_raw, dim3((npix + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, depth, surfel,
+                           p.max_rel_jump);
+        UPS_CHECK_HIP(hipGetLastError());
+        return UPS_OK;
+    }
+    const dim3 grid(g.cols / kTileW, (g.rows + kTileH - 1) / kTileH);
     // ping-pong so that the last level writes `surfel`
-    float4 *raw = (L % 2 == 0) ? surfel : ctx->tmp_surfel;
-    hipLaunchKernelGGL(k_normals_raw, dim3((npix + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, depth, raw,
-                       p.max_rel_jump);
+    float4 *bufs[2] = {surfel, ctx->tmp_surfel};
+    float4 *dst = bufs[(L - 1) % 2];
+    hipLaunchKernelGGL(k_normals_atrous, grid, dim3(kBlock), 0, s, g, depth, dst, p.max_rel_jump, inv_sr, inv_sn2);
     UPS_CHECK_HIP(hipGetLastError());
-    const float4 *src = raw;
-    for (int l = 0; l < L; l++) {
-        float4 *dst = ((L - 1 - l) % 2 == 0) ? bufs[0] : bufs[1];
+    const float4 *src = dst;
+    for (int l = 1; l < L; l++) {
+        dst = bufs[(L - 1 - l) % 2];
         const int step = 1 << l;
         const size_t lds = (size_t)(kTileW + 4 * step) * (kTileH + 4 * step) * sizeof(float4);
-        dim3 grid(g.cols / kTileW, (g.rows + kTileH - 1) / kTileH);
-        hipLaunchKernelGGL(k_atrous, grid, dim3(kBlock), lds, s, g, src, dst, step, 1.f / p.sigma_r,
-                           1.f / (p.sigma_n * p.sigma_n));
+        hipLaunchKernelGGL(k_atrous, grid, dim3(kBlock), lds, s, g, src, dst, step, inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         src = dst;
     }

@@ -344,3 +344,27 @@ def test_fuse_parity(gpu_lib, ctx, c0, c0_surfels, torch_mod):
     assert dn.max() < 1e-4, dn.max()
     filled = (cnt == 0) & (co == 1)
     assert filled.sum() > 100
+
+
+def test_fuse_twice_matches_oracle(gpu_lib, ctx, c0, c0_surfels):
+    """Two fusions in a row into an initially empty keyframe (the first fills
+    it, the second updates it and fills what is still empty): the fill keys
+    must be clean for the second call."""
+    kf, scan = c0_surfels
+    g = c0["geom"]
+    T = c0["T_gt"]
+    kf_d = _t(np.zeros_like(kf))
+    cnt_d = _t(np.zeros(g.shape, np.int16))
+    ko = np.zeros(kf.shape)
+    co = np.zeros(g.shape, np.uint16)
+    for src, pose in ((kf, np.eye(4)), (scan, T)):
+        gpu_lib.fuse_scan(ctx, g, _t(src), g, kf_d, cnt_d, pose)
+        ko, co = O.fuse(g, src, g, ko, co, pose)
+    cg = _np(cnt_d).view(np.uint16)
+    mism = int((cg != co).sum())
+    assert mism <= 2e-3 * cg.size, mism
+    assert (co == 2).sum() > 0.5 * cg.size
+    same = (cg == co) & (co > 0)
+    kg = _np(kf_d)
+    dr = np.abs(kg[..., 3][same] - ko[..., 3][same]) / ko[..., 3][same]
+    assert dr.max() < 1e-5
