@@ -1,26 +1,32 @@
 """Benchmark of the registration hot path on one MI355X.
 
-Workload (sensor scale): a 128x1024 scan (+-22.5 deg elevation) of a synthetic
-outdoor scene -- ground with 5 cm gradient-noise relief, 200 vertical
-cylinders, 4 building facades -- registered against a keyframe fused from 10
-scans along a 5 m path, 3-level coarse-to-fine pyramid with 10/10/10
-Gauss-Newton iterations from the previous scan's pose, then fused into the
+Headline workload (sensor scale): a 128x1024 scan (+-22.5 deg elevation) of a
+synthetic outdoor scene -- ground with 5 cm gradient-noise relief, 200
+vertical cylinders, 4 building facades -- registered against a keyframe fused
+from 10 scans along a 5 m path; 3-level coarse-to-fine pyramid with 10/10/10
+Gauss-Newton iterations from the previous scan's pose; then fused into the
 keyframe.  One step = normals of the scan + registration (pyramids, 30
 iterations, quality) + keyframe fusion, replayed from a HIP graph with every
-input resident in device memory.
+input resident in device memory.  value = ICP pixel-iterations per second over
+the whole step (1,720,320 pixel-iterations per step); ms_per_step = ms per
+128x1024 registration.
 
-metric value = ICP pixel-iterations per second over the whole step
-(1,720,320 pixel-iterations per step); ms_per_step = ms per 128x1024
-registration.  The roofline object covers the level-0 ICP iteration kernel;
-the cpu_baseline object times the FP64 oracle on the host for the same step.
+Second workload (batched): 256 independent registrations of panorama pairs
+of sizes drawn from {64x512, 64x1024, 128x1024, 128x2048} (box room or
+outdoor scene, motions up to 10 deg / 1 m), identity start, 3 levels of at
+most 10 iterations with an early exit below a 1e-6 update norm.  One step =
+normals of all 512 panoramas + all 256 registrations, replayed from a graph.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+The roofline objects cover the level-0 Gauss-Newton launch of each workload
+(timed with HIP events on its own stream); the cpu_baseline object times the
+FP64 oracle on the host for the headline step.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batch]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import platform
 import subprocess
@@ -35,6 +41,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 LEVELS = 3
 ITERS = (10, 10, 10)
+N_BATCH = 256
+BYTES_PER_PIXEL = 16  # one float4 surfel streamed per scan pixel ...
+BYTES_PER_GATHER = 16  # ... and one keyframe surfel gathered per projected scan surfel
+PREC = {"kahan": 0, "f32": 1, "f64": 2}
+PREC_NAME = {"kahan": "Kahan FP32 -> FP64", "f32": "FP32", "f64": "FP64 accumulation"}
 
 
 def parse():
@@ -43,8 +54,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--precision", choices=["kahan", "f32", "f64"], default="kahan",
+                    help="reduction precision: Kahan FP32 -> FP64, pure FP32, or FP64 accumulation")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2101_00585_amd", "autotune_gfx950.json"))
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_info():
@@ -74,7 +94,7 @@ def cpu_baseline(c1, budget_s):
     import oracle as O
     g = c1["geom"]
     # keyframe (setup, untimed): oracle normals of the 10 keyframe scans in
-    # parallel worker processes, then oracle fusion in order
+    # worker processes, then oracle fusion in order
     with concurrent.futures.ProcessPoolExecutor(max_workers=min(10, os.cpu_count() or 1),
                                                 mp_context=mp.get_context("spawn")) as ex:
         surf = list(ex.map(_oracle_surfel, [(g, d) for d in c1["kf_scans"]]))
@@ -96,24 +116,39 @@ def cpu_baseline(c1, budget_s):
     return n, dt, r
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
+def time_graph(torch, graph, stream, reps):
+    """Average ms of one replay, HIP events on the graph's stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        graph.replay()
+        e0.record(stream)
+        for _ in range(reps):
+            graph.replay()
+        e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
 
-    import paper_2101_00585_amd as ups
-    import synth
-    from synth import workloads as W
 
-    ups.load()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    print("[bench] building the sensor-scale workload", file=sys.stderr, flush=True)
+def capture(torch, stream, fn):
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=stream):
+            fn()
+    torch.cuda.synchronize()
+    return g
+
+
+# ----------------------------------------------------------------------------
+# headline: one sensor-scale registration
+# ----------------------------------------------------------------------------
+
+def run_single(args, torch, ups, synth, W, stream):
+    log("building the sensor-scale workload")
     c1 = W.config1()
     g = c1["geom"]
+    dev = torch.device("cuda:0")
     npix = g.rows * g.cols
     ctx = ups.Context(0, max_pixels=npix)
 
@@ -132,7 +167,7 @@ def main():
     cnt_work = cnt_base.clone()
     init_d = ups.pose_tensor(c1["T_init"], dev)
     result = ups.new_result(dev)
-    params = ups.IcpParams(levels=LEVELS, iters=ITERS)
+    params = ups.IcpParams(levels=LEVELS, iters=ITERS, precision=PREC[args.precision])
 
     def step():
         ups.panorama_normals(ctx, g, scan_depth, scan_surf)
@@ -146,18 +181,9 @@ def main():
     torch.cuda.synchronize()
     res = ups.read_result(result)
     rot, tr = synth.pose_error(res["T"], c1["T_gt"])
-
-    stream = torch.cuda.Stream()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(stream):
-        step()  # warm the capture stream
-        torch.cuda.synchronize()
-        with torch.cuda.graph(graph, stream=stream):
-            step()
+    graph = capture(torch, stream, step)
     for _ in range(3):
         graph.replay()
-    torch.cuda.synchronize()
-
     # timed region: K graph replays
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,80 +194,179 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     px_it = sum(ITERS[l] * (g.rows >> l) * (g.cols >> l) for l in range(LEVELS))
     value = px_it / (ms_per_step / 1e3)
-    print(f"[bench] step {ms_per_step:.4f} ms, {value / 1e9:.3f} G px-it/s, pose vs truth {rot:.2e} rad "
-          f"{tr:.2e} m", file=sys.stderr, flush=True)
+    log(f"single: {ms_per_step:.4f} ms/step, {value / 1e9:.3f} G px-it/s, pose vs truth {rot:.2e} rad {tr:.2e} m")
 
-    # ---- dominant kernel: the level-0 ICP iteration, timed with HIP events on
-    # its own stream as the difference of two graphs (N and 0 iterations)
-    def icp_graph(n_iter):
-        gr = torch.cuda.CUDAGraph()
-        p = ups.IcpParams(levels=1, iters=(n_iter,))
-        with torch.cuda.stream(stream):
-            ups.register_scan(ctx, g, scan_surf, g, kf_base, result_pose_t, p, res_k)
-            torch.cuda.synchronize()
-            with torch.cuda.graph(gr, stream=stream):
-                ups.register_scan(ctx, g, scan_surf, g, kf_base, result_pose_t, p, res_k)
-        return gr
-
+    # dominant kernel: the level-0 Gauss-Newton launch, timed as the
+    # difference of two graphs (N and 0 level-0 iterations)
     res_k = ups.new_result(dev)
-    result_pose_t = ups.pose_tensor(c1["T_init"], dev)
+    init_k = ups.pose_tensor(c1["T_init"], dev)
     n_it = 200
-    g_n, g_0 = icp_graph(n_it), icp_graph(0)
 
-    def time_graph(gr, reps=20):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            gr.replay()
-            e0.record(stream)
-            for _ in range(reps):
-                gr.replay()
-            e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
+    def icp_only(n):
+        p = ups.IcpParams(levels=1, iters=(n,), precision=PREC[args.precision])
+        return lambda: ups.register_scan(ctx, g, scan_surf, g, kf_base, init_k, p, res_k)
 
-    t_n, t_0 = time_graph(g_n), time_graph(g_0)
+    t_n = time_graph(torch, capture(torch, stream, icp_only(n_it)), stream, 10)
+    t_0 = time_graph(torch, capture(torch, stream, icp_only(0)), stream, 10)
     icp_us = (t_n - t_0) / n_it * 1e3
     idx, _ = ups.correspondences(ctx, g, scan_surf, g, kf_base, ups.result_pose(result))
     torch.cuda.synchronize()
     gathers = int((idx >= 0).sum().item())
-    alg_bytes = 16 * npix + 16 * gathers
+    alg_bytes = BYTES_PER_PIXEL * npix + BYTES_PER_GATHER * gathers
     achieved = alg_bytes / (icp_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_icp<K=1,Kahan-FP64,iter> level 0 128x1024",
-                "kernel_us": round(icp_us, 3), "algorithmic_bytes_per_launch": alg_bytes,
-                "note": "128x1024 working set (4.2 MB) is cache-resident and launch/latency bound"}
+                "kernel": f"k_icp_one<2,{args.precision},iter> (level-0 Gauss-Newton launch, 128x1024)",
+                "launch_us": round(icp_us, 3), "algorithmic_bytes_per_launch": alg_bytes,
+                "note": "one 128x1024 registration: 4 MB per launch, cache-resident and latency bound"}
+    ctx.close()
+    return dict(c1=c1, value=value, ms_per_step=ms_per_step, px_it=px_it, rot=rot, tr=tr, res=res,
+                roofline=roofline)
 
+
+# ----------------------------------------------------------------------------
+# batched: 256 registrations of uneven sizes
+# ----------------------------------------------------------------------------
+
+def run_batch(args, torch, ups, synth, W, stream):
+    log(f"building the {N_BATCH}-pair batch workload")
+    t0 = time.perf_counter()
+    pairs = W.batch(N_BATCH)
+    log(f"rendered {N_BATCH} pairs in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    tot_px = sum(p["geom"].rows * p["geom"].cols for p in pairs)
+    ctx = ups.Context(0, max_pixels=128 * 2048, max_batch=N_BATCH, max_batch_pixels=tot_px)
+    tune = "measured"
+    if os.path.exists(args.tune_cache):
+        tune = "cache"
+    ups.autotune(ctx, args.tune_cache)
+    items = []
+    for p in pairs:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g, scan_depth=torch.from_numpy(p["scan"]).to(dev),
+                          kf_depth=torch.from_numpy(p["kf"]).to(dev),
+                          scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev),
+                          kf_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev)))
+    params = ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6, precision=PREC[args.precision])
+    batch = ups.Batch(ctx, items, params)
+    init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
+    results = torch.zeros((N_BATCH, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
+
+    def step():
+        batch.normals()
+        batch.register(init, results)
+
+    step()
+    torch.cuda.synchronize()
+    res = ups.read_results(results)
+    graph = capture(torch, stream, step)
+    ms = time_graph(torch, graph, stream, args.batch_steps)
+    errs = np.array([synth.pose_error(r["T"], p["T_gt"]) for r, p in zip(res, pairs)])
+    px_it = 0
+    for r, p in zip(res, pairs):
+        g = p["geom"]
+        px_it += sum(r["level_iters"][l] * (g.rows >> l) * (g.cols >> l) for l in range(LEVELS))
+    eq128 = tot_px / (128 * 1024)
+    log(f"batch: {ms:.3f} ms per {N_BATCH} registrations, {N_BATCH / ms * 1e3:.0f} reg/s, "
+        f"{ms / eq128 * 1e3:.2f} us per 128x1024-equivalent, {px_it / (ms * 1e-3) / 1e9:.1f} G px-it/s")
+
+    # dominant kernel: the batched level-0 Gauss-Newton launch at a fixed
+    # iteration count (no early exit), difference of two graphs
+    def fixed(n):
+        b = ups.Batch(ctx, items, ups.IcpParams(levels=1, iters=(n,), precision=PREC[args.precision]),
+                      batch.pixels_per_thread()[0])
+        r = torch.zeros((N_BATCH, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
+        return b, r
+
+    n_it = 20
+    b_n, r_n = fixed(n_it)
+    b_0, r_0 = fixed(0)
+    t_n = time_graph(torch, capture(torch, stream, lambda: b_n.register(init, r_n)), stream, 5)
+    t_0 = time_graph(torch, capture(torch, stream, lambda: b_0.register(init, r_0)), stream, 5)
+    launch_us = (t_n - t_0) / n_it * 1e3
+    gathers = 0
+    for it, r in zip(items, res):
+        g = it["scan_geom"]
+        idx, _ = ups.correspondences(ctx, g, it["scan_surfel"], g, it["kf_surfel"], ups.pose_tensor(r["T"], dev))
+        gathers += int((idx >= 0).sum().item())
+    alg_bytes = BYTES_PER_PIXEL * tot_px + BYTES_PER_GATHER * gathers
+    achieved = alg_bytes / (launch_us * 1e-6) / 1e9
+    K = batch.pixels_per_thread()
+    out = {
+        "workload": f"{N_BATCH} registrations, sizes from 64x512/64x1024/128x1024/128x2048, identity start, "
+                    "3 levels <=10/10/10, early exit 1e-6, normals of all 512 panoramas included",
+        "ms_per_batch": round(ms, 4),
+        "registrations_per_s": round(N_BATCH / ms * 1e3, 1),
+        "ms_per_128x1024_equivalent": round(ms / eq128, 5),
+        "pixel_iterations_executed": int(px_it),
+        "pixel_iterations_per_s": round(px_it / (ms * 1e-3), 1),
+        "pose_error_vs_truth_median_rad_m": [float(np.median(errs[:, 0])), float(np.median(errs[:, 1]))],
+        "pose_error_vs_truth_p95_rad_m": [float(np.percentile(errs[:, 0], 95)),
+                                          float(np.percentile(errs[:, 1], 95))],
+        "status_counts": {ups.STATUS[s]: int(sum(r["status"] == s for r in res)) for s in ups.STATUS},
+        "pixels_per_thread_by_level": K[:LEVELS],
+        "autotune": tune,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"k_icp_batch<{K[0]},{args.precision},iter> (level-0 launch over all {N_BATCH})",
+                     "launch_us": round(launch_us, 2), "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    for b in (batch, b_n, b_0):
+        b.close()
+    ctx.close()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2101_00585_amd as ups
+    import synth
+    from synth import workloads as W
+
+    ups.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    single = run_single(args, torch, ups, synth, W, stream)
     out = {
         "metric": "ICP pixel-iterations/sec + ms per 128x1024 scan registration (plain vs batched+learned)",
-        "value": round(value, 1),
+        "value": round(single["value"], 1),
         "unit": "pixel-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(single["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 per-pixel, f64 reduction finish/solve",
+        "dtype": "f32 per-pixel; reduction " + PREC_NAME[args.precision] + ("; f64 solve" if args.precision != "f32"
+                                                                             else "; f32 solve"),
         "data": "synthetic",
         "config": {"workload": "plain single registration, 128x1024 outdoor scene, keyframe fused from 10 scans, "
                                "3-level pyramid 10/10/10 GN iterations + normals + fusion",
-                   "pixel_iterations_per_step": px_it, "ms_per_128x1024_registration": round(ms_per_step, 5),
-                   "pose_error_vs_truth_rad_m": [rot, tr], "parallelism": "none (1 GPU)"},
-        "roofline": roofline,
+                   "pixel_iterations_per_step": single["px_it"],
+                   "ms_per_128x1024_registration": round(single["ms_per_step"], 5),
+                   "pose_error_vs_truth_rad_m": [single["rot"], single["tr"]], "parallelism": "none (1 GPU)"},
+        "roofline": single["roofline"],
     }
+    if not args.no_batch:
+        out["batched"] = run_batch(args, torch, ups, synth, W, stream)
     if not args.no_cpu_baseline:
         model, ncpu = cpu_info()
-        print(f"[bench] cpu baseline (oracle, 1 thread) on {model}", file=sys.stderr, flush=True)
-        n, dt, r_orc = cpu_baseline(c1, args.cpu_seconds)
-        out["cpu_baseline"] = {"value": round(n * px_it / dt, 1), "unit": "pixel-iterations/s", "cores": 1,
-                               "kind": "oracle",
+        log(f"cpu baseline (oracle, 1 thread) on {model}")
+        n, dt, r_orc = cpu_baseline(single["c1"], args.cpu_seconds)
+        out["cpu_baseline"] = {"value": round(n * single["px_it"] / dt, 1), "unit": "pixel-iterations/s",
+                               "cores": 1, "kind": "oracle",
                                "sample": f"{n} full steps (normals + 3-level 30-iteration registration + fusion) "
                                          f"of the same 128x1024 workload in {dt:.1f} s, FP64, single thread, "
                                          f"host: {model}, {ncpu} logical CPUs",
                                "ms_per_step": round(dt / n * 1e3, 2)}
-        rot_o, tr_o = synth.pose_error(res["T"], r_orc["T"])
+        rot_o, tr_o = synth.pose_error(single["res"]["T"], r_orc["T"])
         out["config"]["pose_gpu_vs_oracle_rad_m"] = [rot_o, tr_o]
     print(json.dumps(out), flush=True)
 

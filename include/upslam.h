@@ -64,9 +64,13 @@ enum {
 
 /* ups_icp_params.precision values */
 enum {
-    UPS_PREC_KAHAN_F64 = 0, /* FP32 per pixel, Kahan-compensated FP32 per-thread sums,
-                               FP64 cross-lane/block/grid sums, FP64 solve and pose update */
-    UPS_PREC_F32 = 1        /* FP32 everywhere, including the solve and the pose update */
+    UPS_PREC_KAHAN_F64 = 0, /* FP32 per pixel; per-thread FP32 sums, Kahan-compensated for J^T r,
+                               sum r^2 and the truncated cost (plain for J^T J); FP64 cross-lane,
+                               block and grid sums, FP64 solve and pose update */
+    UPS_PREC_F32 = 1,       /* FP32 everywhere, including the solve and the pose update */
+    UPS_PREC_F64 = 2        /* FP32 per pixel, per-thread sums of the (exact) FP64 products in FP64,
+                               FP64 beyond: on gfx950 an FP64 FMA issues at the FP32 rate, so this
+                               is cheaper than the compensated FP32 sums and more accurate */
 };
 
 typedef struct {
@@ -121,6 +125,7 @@ typedef struct {
     double rms, trunc_cost, inlier_ratio;
     int64_t inliers, valid;
     int32_t iters_run, status;
+    int32_t level_iters[4]; /* updates applied at each pyramid level */
     double JtJ[21], Jtr[6];
     double last_update_norm;
 } ups_icp_result;
@@ -190,11 +195,70 @@ ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const f
                                const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
                                float cos_theta_max, int32_t *kf_index_d, uint8_t *inlier_d, void *stream);
 
+/* Spherical projection (the lookup behind the projective correspondences of
+ * Section III-B): for each of n points xyz_d[n][3] (FP32, the panorama's
+ * sensor frame) the nearest pixel centre, i_d[k] = row and j_d[k] = column,
+ * or -1 / -1 for the origin and for directions outside the panorama's rows. */
+ups_status ups_project_points(ups_context *ctx, const ups_geom *g, const float *xyz_d, int64_t n, int32_t *i_d,
+                              int32_t *j_d, void *stream);
+
 /* Gauss-Newton normal equations of Equation 1 at a fixed pose at level 0, with
  * the given precision mode's reduction (UPS_PREC_*). */
 ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
                                 const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
                                 float cos_theta_max, int32_t precision, ups_normal_eq *out_d, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent registrations of uneven panorama sizes (e.g. the
+ * candidate transforms of a loop-closure search, Section III-C) advanced
+ * together.  One launch per Gauss-Newton iteration covers every registration
+ * of the batch; a registration that met its stop criterion or failed drops out
+ * of the remaining launches.  The launch sequence is fixed at planning time,
+ * so a whole ups_register_batch call can be captured in a HIP graph.
+ * ------------------------------------------------------------------------ */
+
+/* One registration of a batch.  scan_surfel_d / kf_surfel_d are the surfel
+ * images the registration reads; when scan_depth_d / kf_depth_d are not NULL,
+ * ups_batch_normals writes the surfel images from them. */
+typedef struct {
+    ups_geom scan_g, kf_g;
+    const float *scan_depth_d, *kf_depth_d;
+    float *scan_surfel_d, *kf_surfel_d;
+} ups_batch_item;
+
+typedef struct ups_batch ups_batch;
+
+/* Plan a batch of n registrations sharing the parameters p: validates the
+ * items, uploads their descriptors and allocates the batch's scratch
+ * (pyramids, states, partials).  Synchronous; not for use during capture.
+ * pixels_per_thread: a power of two up to 64, or 0 for the library's choice
+ * (the autotuned value for these sizes if ups_autotune has run).  Every item
+ * must satisfy the ups_register_scan constraints and have at most
+ * 256 * 256 * 64 pixels. */
+ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *items_h, const ups_icp_params *p,
+                            int32_t pixels_per_thread, ups_batch **out);
+void ups_batch_destroy(ups_batch *b);
+
+/* Surfel images (Section III-A) of every item that has depth pointers, one
+ * launch per a-trous level over all of them. */
+ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_params *p, void *stream);
+
+/* Run every registration of the batch from init_d[n] (device poses) and write
+ * results_d[n] (device).  Same numerics as ups_register_scan. */
+ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d,
+                              void *stream);
+
+/* Autotune the pixels per thread of batch launches for this device: times the
+ * Gauss-Newton launch at 1, 2, 4, ..., 64 pixels per thread on synthetic
+ * batches of each lidar panorama size (16x128 ... 128x2048) and keeps the
+ * fastest per size in the context for later ups_batch_create calls.  With a
+ * cache path, a cache written for the same GPU architecture is loaded instead
+ * of measuring, and a fresh measurement is written there as JSON.
+ * Synchronous; allocates temporary device memory. */
+ups_status ups_autotune(ups_context *ctx, const char *cache_json_path);
+
+/* Pixels per thread the batch launches use at each pyramid level. */
+ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]);
 
 #ifdef __cplusplus
 }

@@ -80,7 +80,8 @@ class _IcpParams(ctypes.Structure):
 class _IcpResult(ctypes.Structure):
     _fields_ = [("T", ctypes.c_double * 12), ("rms", ctypes.c_double), ("trunc_cost", ctypes.c_double),
                 ("inlier_ratio", ctypes.c_double), ("inliers", ctypes.c_int64), ("valid", ctypes.c_int64),
-                ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("JtJ", ctypes.c_double * 21),
+                ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("level_iters", ctypes.c_int32 * 4),
+                ("JtJ", ctypes.c_double * 21),
                 ("Jtr", ctypes.c_double * 6), ("last_update_norm", ctypes.c_double)]
 
 
@@ -297,6 +298,7 @@ def register(sg, scan, kg, kf, init, params: IcpParams | None = None) -> dict:
                         ctypes.byref(pc), ctypes.byref(res))
     return dict(T=pose44(res.T), rms=res.rms, trunc_cost=res.trunc_cost, inlier_ratio=res.inlier_ratio,
                 inliers=res.inliers, valid=res.valid, iters_run=res.iters_run, status=res.status,
+                level_iters=list(res.level_iters),
                 JtJ=np.array(res.JtJ[:]), Jtr=np.array(res.Jtr[:]), last_update_norm=res.last_update_norm)
 
 

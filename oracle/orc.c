@@ -422,6 +422,7 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
     memcpy(T, init, sizeof(T));
     int status = ORC_CONVERGED;
     int iters = 0;
+    int level_iters[4] = {0, 0, 0, 0};
     double last_norm = 0.0;
     int stop = 0;
     for (int l = p->levels - 1; l >= 0 && !stop; l--) {
@@ -449,6 +450,7 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
             orc_exp_se3(xi, E);
             orc_compose(E, T, T);
             iters++;
+            level_iters[l]++;
             double nrm = 0.0;
             for (int k = 0; k < 6; k++) nrm += xi[k] * xi[k];
             last_norm = sqrt(nrm);
@@ -495,6 +497,7 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
     res->rms = n_in > 0 ? sqrt(s2 / (double)n_in) : 0.0;
     res->trunc_cost = trunc;
     res->iters_run = iters;
+    memcpy(res->level_iters, level_iters, sizeof(level_iters));
     res->status = status;
     memcpy(res->JtJ, A, sizeof(A));
     memcpy(res->Jtr, b, sizeof(b));

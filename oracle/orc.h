@@ -51,6 +51,7 @@ typedef struct {
     double rms, trunc_cost, inlier_ratio;
     int64_t inliers, valid;
     int32_t iters_run, status;
+    int32_t level_iters[4];
     double JtJ[21], Jtr[6];
     double last_update_norm;
 } orc_icp_result;

@@ -28,6 +28,7 @@ _LIB = None
 STATUS = {0: "CONVERGED", 1: "MAX_ITERS", 2: "DEGENERATE", 3: "NO_INLIERS", 4: "FALLBACK_USED"}
 PREC_KAHAN_F64 = 0
 PREC_F32 = 1
+PREC_F64 = 2
 
 
 class UpsError(RuntimeError):
@@ -61,7 +62,8 @@ class ups_icp_params(ctypes.Structure):
 class ups_icp_result(ctypes.Structure):
     _fields_ = [("T", ups_pose), ("rms", ctypes.c_double), ("trunc_cost", ctypes.c_double),
                 ("inlier_ratio", ctypes.c_double), ("inliers", ctypes.c_int64), ("valid", ctypes.c_int64),
-                ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("JtJ", ctypes.c_double * 21),
+                ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("level_iters", ctypes.c_int32 * 4),
+                ("JtJ", ctypes.c_double * 21),
                 ("Jtr", ctypes.c_double * 6), ("last_update_norm", ctypes.c_double)]
 
 
@@ -73,6 +75,12 @@ class ups_normal_eq(ctypes.Structure):
 class ups_fuse_params(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_float), ("cos_theta_max", ctypes.c_float),
                 ("min_cos_incidence", ctypes.c_float), ("max_count", ctypes.c_int32)]
+
+
+class ups_batch_item(ctypes.Structure):
+    _fields_ = [("scan_g", ups_geom), ("kf_g", ups_geom), ("scan_depth_d", ctypes.c_void_p),
+                ("kf_depth_d", ctypes.c_void_p), ("scan_surfel_d", ctypes.c_void_p),
+                ("kf_surfel_d", ctypes.c_void_p)]
 
 
 RESULT_BYTES = ctypes.sizeof(ups_icp_result)
@@ -97,11 +105,19 @@ def load():
         "ups_fuse_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_correspondences": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
         "ups_normal_equations": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P, _P],
+        "ups_project_points": [_P, _P, _P, ctypes.c_int64, _P, _P, _P],
+        "ups_batch_create": [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)],
+        "ups_batch_normals": [_P, _P, _P, _P],
+        "ups_register_batch": [_P, _P, _P, _P, _P],
+        "ups_batch_pixels_per_thread": [_P, _P],
+        "ups_autotune": [_P, ctypes.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.ups_batch_destroy.argtypes = [_P]
+    lib.ups_batch_destroy.restype = None
     lib.ups_context_destroy.argtypes = [_P]
     lib.ups_context_destroy.restype = None
     lib.ups_last_error.argtypes = []
@@ -239,14 +255,7 @@ def new_result(device="cuda"):
 
 
 def read_result(res) -> dict:
-    raw = bytes(res.detach().cpu().numpy().tobytes())
-    r = ups_icp_result.from_buffer_copy(raw)
-    T = np.eye(4)
-    T[:3, :3] = np.array(r.T.R[:]).reshape(3, 3)
-    T[:3, 3] = np.array(r.T.t[:])
-    return dict(T=T, rms=r.rms, trunc_cost=r.trunc_cost, inlier_ratio=r.inlier_ratio, inliers=r.inliers,
-                valid=r.valid, iters_run=r.iters_run, status=r.status, JtJ=np.array(r.JtJ[:]),
-                Jtr=np.array(r.Jtr[:]), last_update_norm=r.last_update_norm)
+    return read_result_bytes(bytes(res.detach().cpu().numpy().tobytes()))
 
 
 def read_neq(t) -> dict:
@@ -335,6 +344,19 @@ def correspondences(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T,
     return idx, inl
 
 
+def project_points(ctx: Context, geom, xyz):
+    """Nearest pixel (row, col) of each point of a float32 [N, 3] tensor;
+    -1 where there is none."""
+    torch = _torch()
+    n = xyz.shape[0]
+    ii = torch.empty(n, dtype=torch.int32, device=xyz.device)
+    jj = torch.empty(n, dtype=torch.int32, device=xyz.device)
+    g = geom_c(geom)
+    _check(_LIB.ups_project_points(ctx.handle, ctypes.byref(g), _dev_ptr(xyz, torch.float32, "points"), int(n),
+                                   _dev_ptr(ii, torch.int32, "rows"), _dev_ptr(jj, torch.int32, "cols"), _stream()))
+    return ii, jj
+
+
 def normal_equations(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T, d_max=0.5,
                      cos_theta_max=math.cos(math.radians(30.0)), precision=PREC_KAHAN_F64):
     torch = _torch()
@@ -348,3 +370,93 @@ def normal_equations(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T
                                      int(precision), _dev_ptr(out, torch.uint8, "out"), _stream()))
     out._keep = T_t
     return out
+
+
+# ----------------------------------------------------------------------------
+# batches
+# ----------------------------------------------------------------------------
+
+def autotune(ctx: Context, cache_path: str | None = None):
+    """Measure (or load from ``cache_path``) the pixels per thread of batch
+    launches for this GPU."""
+    _check(_LIB.ups_autotune(ctx.handle, cache_path.encode() if cache_path else None))
+
+
+class Batch:
+    """A planned batch of registrations.  ``items``: dicts with ``scan_geom``,
+    ``kf_geom``, device ``scan_surfel`` / ``kf_surfel`` float32 [rows, cols, 4]
+    tensors and optional ``scan_depth`` / ``kf_depth`` float32 [rows, cols]
+    tensors (for ``normals``).  The tensors must stay alive while the batch
+    is used."""
+
+    def __init__(self, ctx: Context, items, params: IcpParams | None = None, pixels_per_thread: int = 0):
+        torch = _torch()
+        self.ctx = ctx
+        self.n = len(items)
+        self.items = items
+        arr = (ups_batch_item * self.n)()
+        for k, it in enumerate(items):
+            a = arr[k]
+            a.scan_g = geom_c(it["scan_geom"])
+            a.kf_g = geom_c(it["kf_geom"])
+            a.scan_surfel_d = _dev_ptr(it["scan_surfel"], torch.float32, "scan surfel").value
+            a.kf_surfel_d = _dev_ptr(it["kf_surfel"], torch.float32, "keyframe surfel").value
+            a.scan_depth_d = _dev_ptr(it["scan_depth"], torch.float32, "scan depth").value \
+                if it.get("scan_depth") is not None else None
+            a.kf_depth_d = _dev_ptr(it["kf_depth"], torch.float32, "keyframe depth").value \
+                if it.get("kf_depth") is not None else None
+        self.params = params or IcpParams()
+        pc = self.params.c()
+        h = _P()
+        _check(_LIB.ups_batch_create(ctx.handle, self.n, ctypes.cast(arr, _P), ctypes.byref(pc),
+                                     int(pixels_per_thread), ctypes.byref(h)))
+        self._h = h
+
+    def pixels_per_thread(self):
+        out = (ctypes.c_int32 * 4)()
+        _check(_LIB.ups_batch_pixels_per_thread(self._h, out))
+        return list(out)
+
+    def normals(self, params: NormalParams | None = None):
+        p = (params or NormalParams()).c()
+        _check(_LIB.ups_batch_normals(self.ctx.handle, self._h, ctypes.byref(p), _stream()))
+
+    def register(self, init, results=None):
+        """``init``: device float64 [n, 12] poses (or a list of 4x4).  Returns
+        the device results buffer [n, RESULT_BYTES] (``read_results``)."""
+        torch = _torch()
+        if not isinstance(init, torch.Tensor):
+            init = torch.stack([pose_tensor(T) for T in init])
+        if results is None:
+            results = torch.zeros((self.n, RESULT_BYTES), dtype=torch.uint8, device=init.device)
+        _check(_LIB.ups_register_batch(self.ctx.handle, self._h, _dev_ptr(init, torch.float64, "init poses"),
+                                       _dev_ptr(results, torch.uint8, "results"), _stream()))
+        results._keep = init
+        return results
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.ups_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def read_results(results) -> list:
+    raw = results.detach().cpu().numpy()
+    return [read_result_bytes(bytes(raw[k].tobytes())) for k in range(raw.shape[0])]
+
+
+def read_result_bytes(raw: bytes) -> dict:
+    r = ups_icp_result.from_buffer_copy(raw)
+    T = np.eye(4)
+    T[:3, :3] = np.array(r.T.R[:]).reshape(3, 3)
+    T[:3, 3] = np.array(r.T.t[:])
+    return dict(T=T, rms=r.rms, trunc_cost=r.trunc_cost, inlier_ratio=r.inlier_ratio, inliers=r.inliers,
+                valid=r.valid, iters_run=r.iters_run, status=r.status, level_iters=list(r.level_iters),
+                JtJ=np.array(r.JtJ[:]),
+                Jtr=np.array(r.Jtr[:]), last_update_norm=r.last_update_norm)

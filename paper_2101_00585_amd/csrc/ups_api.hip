@@ -94,6 +94,11 @@ ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream
     d.az_scale = (float)((double)d.cols / (2.0 * M_PI));
     d.r_min = (float)g->r_min;
     d.r_max = (float)g->r_max;
+    {
+        const double dl = g->d_el * s, half = 0.5 * dl;
+        const double top = g->el_top + half, bottom = g->el_top - (d.rows - 1) * dl - half;
+        d.narrow = (top < M_PI / 4 - 1e-6 && bottom > -M_PI / 4 + 1e-6) ? 1 : 0;
+    }
     d.lut_row = e->row;
     d.lut_col = e->col;
     *out = d;
@@ -207,7 +212,7 @@ static ups_status check_icp_params(const ups_icp_params *p) {
     }
     UPS_REQUIRE(p->cos_theta_max >= -1.f && p->cos_theta_max <= 1.f, "cos_theta_max must be in [-1, 1]");
     UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
-    UPS_REQUIRE(p->precision == UPS_PREC_KAHAN_F64 || p->precision == UPS_PREC_F32, "unknown precision mode");
+    UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
     return UPS_OK;
 }
 
@@ -308,6 +313,23 @@ ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const f
                                   cos_theta_max, kf_index_d, inlier_d, (hipStream_t)stream);
 }
 
+ups_status ups_project_points(ups_context *ctx, const ups_geom *g, const float *xyz_d, int64_t n, int32_t *i_d,
+                              int32_t *j_d, void *stream) {
+    UPS_REQUIRE(ctx, "context is null");
+    UPS_REQUIRE(n >= 0 && n <= ((int64_t)1 << 31) - kBlock, "n out of range");
+    ups_status st;
+    if (n > 0) {
+        if ((st = check_ptr(xyz_d, 4, "points")) != UPS_OK) return st;
+        if ((st = check_ptr(i_d, 4, "rows")) != UPS_OK) return st;
+        if ((st = check_ptr(j_d, 4, "cols")) != UPS_OK) return st;
+    }
+    DeviceGuard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    DGeom d;
+    if ((st = device_geom(ctx, g, 0, (hipStream_t)stream, &d)) != UPS_OK) return st;
+    return launch_project_points(d, xyz_d, n, i_d, j_d, (hipStream_t)stream);
+}
+
 ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
                                 const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
                                 float cos_theta_max, int32_t precision, ups_normal_eq *out_d, void *stream) {
@@ -318,7 +340,7 @@ ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const 
     if ((st = check_ptr(T_d, 8, "pose")) != UPS_OK) return st;
     if ((st = check_ptr(out_d, 8, "out")) != UPS_OK) return st;
     UPS_REQUIRE(d_max > 0.f, "d_max must be > 0");
-    UPS_REQUIRE(precision == UPS_PREC_KAHAN_F64 || precision == UPS_PREC_F32, "unknown precision mode");
+    UPS_REQUIRE(precision >= UPS_PREC_KAHAN_F64 && precision <= UPS_PREC_F64, "unknown precision mode");
     DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     if ((int64_t)scan_g->rows * scan_g->cols > ctx->max_pixels) {

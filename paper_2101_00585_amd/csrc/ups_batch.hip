@@ -1,0 +1,315 @@
+// Batches of independent registrations (C ABI: ups_batch_*, ups_register_batch).
+//
+// Planning (ups_batch_create) lays out every registration's descriptor, its
+// pyramid levels, two state slots and two partial buffers in device memory,
+// plus one prefix table of tile counts per pyramid level.  Running
+// (ups_register_batch) is a fixed launch sequence: one prepare launch (states
+// and pyramids of all registrations), one launch per Gauss-Newton iteration
+// covering the tiles of every registration at that level, one evaluation
+// launch and one finish launch (a block per registration).  Registrations
+// whose level converged or that failed leave their tiles idle.
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "ups_icp.hpp"
+
+using namespace ups;
+
+struct ups_batch {
+    int device = 0;
+    int n = 0;
+    ups_icp_params p;
+    int K[4] = {1, 1, 1, 1};
+    int total_tiles[4] = {0, 0, 0, 0};
+    int total_pre = 0;
+    Inst *d_inst = nullptr;       // [n]
+    int *d_tile_start = nullptr;  // [4][n+1]
+    int *d_pre_start = nullptr;   // [n+1]
+    float4 *pyr = nullptr;
+    RegState *state = nullptr;    // [n][2]
+    double *partials = nullptr;   // [n][2][pstride][kPartialStride]
+    // batched normals
+    NormImg *d_nimg = nullptr;
+    int *d_ntile_start = nullptr;
+    float4 *ntmp = nullptr;
+    int n_nimg = 0, total_ntiles = 0;
+};
+
+namespace {
+
+struct Guard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit Guard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~Guard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_batch(ups_batch *b) {
+    (void)hipFree(b->d_inst);
+    (void)hipFree(b->d_tile_start);
+    (void)hipFree(b->d_pre_start);
+    (void)hipFree(b->pyr);
+    (void)hipFree(b->state);
+    (void)hipFree(b->partials);
+    (void)hipFree(b->d_nimg);
+    (void)hipFree(b->d_ntile_start);
+    (void)hipFree(b->ntmp);
+    delete b;
+}
+
+// Library choice of pixels per thread for batch launches: the autotuned value
+// if one was recorded for this size, else 8.
+int default_k(ups_context *ctx, int64_t npix) {
+    const int tuned = autotuned_k(ctx, npix);
+    return tuned > 0 ? tuned : 8;
+}
+
+}  // namespace
+
+extern "C" {
+
+ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *items, const ups_icp_params *p,
+                            int32_t pixels_per_thread, ups_batch **out) {
+    UPS_REQUIRE(ctx && items && p && out, "null argument");
+    *out = nullptr;
+    UPS_REQUIRE(n >= 1 && n <= ctx->max_batch, "n must be in [1, the context's max_batch]");
+    UPS_REQUIRE(pixels_per_thread == 0 || (pixels_per_thread <= 64 && (pixels_per_thread & (pixels_per_thread - 1)) == 0),
+                "pixels_per_thread must be 0 or a power of two up to 64");
+    UPS_REQUIRE(p->levels >= 1 && p->levels <= 4, "levels must be in [1, 4]");
+    for (int l = 0; l < p->levels; l++) {
+        UPS_REQUIRE(p->iters[l] >= 0 && p->iters[l] <= 1000, "iters must be in [0, 1000]");
+        UPS_REQUIRE(p->d_max[l] > 0.f, "d_max must be > 0");
+    }
+    UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
+    UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    const int L = p->levels, s = 1 << (L - 1);
+    int64_t total_scan = 0, total_kf = 0, max_npix = 0;
+    for (int k = 0; k < n; k++) {
+        const ups_batch_item &it = items[k];
+        UPS_REQUIRE(it.scan_surfel_d && it.kf_surfel_d, "item " + std::to_string(k) + ": surfel pointers are null");
+        UPS_REQUIRE(((uintptr_t)it.scan_surfel_d % 16) == 0 && ((uintptr_t)it.kf_surfel_d % 16) == 0,
+                    "item " + std::to_string(k) + ": surfel images must be 16-byte aligned");
+        for (const ups_geom *g : {&it.scan_g, &it.kf_g}) {
+            UPS_REQUIRE(g->rows % s == 0 && g->rows / s >= 2 && g->cols % (64 * s) == 0,
+                        "item " + std::to_string(k) + ": rows/cols not divisible for the pyramid");
+        }
+        total_scan += (int64_t)it.scan_g.rows * it.scan_g.cols;
+        total_kf += (int64_t)it.kf_g.rows * it.kf_g.cols;
+        max_npix = std::max(max_npix, (int64_t)it.scan_g.rows * it.scan_g.cols);
+    }
+    if (total_scan > ctx->max_batch_pixels || total_kf > ctx->max_batch_pixels) {
+        set_error("batch panoramas exceed the context's max_batch_pixels");
+        return UPS_ERR_WORKSPACE;
+    }
+    ups_batch *b = new ups_batch();
+    b->device = ctx->device;
+    b->n = n;
+    b->p = *p;
+    for (int l = 0; l < L; l++) {
+        int K = pixels_per_thread ? pixels_per_thread : default_k(ctx, max_npix >> (2 * l));
+        // every registration must fit in 256 tiles at every level
+        while (K < 64 && ((max_npix >> (2 * l)) + kBlock * K - 1) / (kBlock * K) > 256) K *= 2;
+        if (((max_npix >> (2 * l)) + kBlock * K - 1) / (kBlock * K) > 256) {
+            free_batch(b);
+            set_error("a batch panorama is too large for 256 tiles of 64 pixels per thread");
+            return UPS_ERR_INVALID_ARG;
+        }
+        b->K[l] = K;
+    }
+
+    // host descriptors
+    std::vector<Inst> hi(n);
+    std::vector<int> tile_start(4 * (n + 1), 0), pre_start(n + 1, 0);
+    int64_t pyr_total = 0;
+    int pstride = 1;
+    std::vector<int64_t> pyr_off_s(n), pyr_off_k(n);
+    for (int k = 0; k < n; k++) {
+        const ups_batch_item &it = items[k];
+        Inst &I = hi[k];
+        memset(&I, 0, sizeof(I));
+        int pre = 0;
+        for (int l = 0; l < L; l++) {
+            ups_status st;
+            if ((st = device_geom(ctx, &it.scan_g, l, nullptr, &I.sg[l])) != UPS_OK ||
+                (st = device_geom(ctx, &it.kf_g, l, nullptr, &I.kg[l])) != UPS_OK) {
+                free_batch(b);
+                return st;
+            }
+            const int np = I.sg[l].rows * I.sg[l].cols;
+            I.nblocks[l] = (np + kBlock * b->K[l] - 1) / (kBlock * b->K[l]);
+            pstride = std::max(pstride, I.nblocks[l]);
+            if (l > 0) pre += np + I.kg[l].rows * I.kg[l].cols;
+        }
+        pyr_off_s[k] = pyr_total;
+        for (int l = 1; l < L; l++) pyr_total += (int64_t)I.sg[l].rows * I.sg[l].cols;
+        pyr_off_k[k] = pyr_total;
+        for (int l = 1; l < L; l++) pyr_total += (int64_t)I.kg[l].rows * I.kg[l].cols;
+        pre_start[k + 1] = pre_start[k] + pre;
+    }
+    for (int l = 0; l < 4; l++) {
+        for (int k = 0; k < n; k++)
+            tile_start[l * (n + 1) + k + 1] = tile_start[l * (n + 1) + k] + (l < L ? hi[k].nblocks[l] : 0);
+        b->total_tiles[l] = tile_start[l * (n + 1) + n];
+    }
+    b->total_pre = pre_start[n];
+
+    // batched-normals images: every scan / keyframe with a depth pointer
+    std::vector<NormImg> nimg;
+    std::vector<int> ntile_start(1, 0);
+    int64_t ntmp_total = 0;
+    for (int k = 0; k < n; k++) {
+        const ups_batch_item &it = items[k];
+        if (it.scan_depth_d) {
+            nimg.push_back(NormImg{hi[k].sg[0], it.scan_depth_d, (float4 *)it.scan_surfel_d, nullptr});
+            ntmp_total += (int64_t)hi[k].sg[0].rows * hi[k].sg[0].cols;
+        }
+        if (it.kf_depth_d) {
+            nimg.push_back(NormImg{hi[k].kg[0], it.kf_depth_d, (float4 *)it.kf_surfel_d, nullptr});
+            ntmp_total += (int64_t)hi[k].kg[0].rows * hi[k].kg[0].cols;
+        }
+    }
+
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void **ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, bytes > 0 ? bytes : 16);
+    };
+    alloc((void **)&b->d_inst, n * sizeof(Inst));
+    alloc((void **)&b->d_tile_start, tile_start.size() * sizeof(int));
+    alloc((void **)&b->d_pre_start, pre_start.size() * sizeof(int));
+    alloc((void **)&b->pyr, std::max<int64_t>(pyr_total, 1) * sizeof(float4));
+    alloc((void **)&b->state, (size_t)n * 2 * sizeof(RegState));
+    alloc((void **)&b->partials, (size_t)n * 2 * pstride * kPartialStride * sizeof(double));
+    if (!nimg.empty()) {
+        alloc((void **)&b->d_nimg, nimg.size() * sizeof(NormImg));
+        alloc((void **)&b->ntmp, ntmp_total * sizeof(float4));
+    }
+    if (e != hipSuccess) {
+        free_batch(b);
+        set_error(std::string("batch allocation failed: ") + hipGetErrorString(e));
+        return UPS_ERR_HIP;
+    }
+    for (int k = 0; k < n; k++) {
+        Inst &I = hi[k];
+        I.scan[0] = (const float4 *)items[k].scan_surfel_d;
+        I.kf[0] = (const float4 *)items[k].kf_surfel_d;
+        int64_t os = pyr_off_s[k], ok = pyr_off_k[k];
+        for (int l = 1; l < L; l++) {
+            I.scan[l] = b->pyr + os;
+            os += (int64_t)I.sg[l].rows * I.sg[l].cols;
+            I.kf[l] = b->pyr + ok;
+            ok += (int64_t)I.kg[l].rows * I.kg[l].cols;
+        }
+        I.state = b->state + 2 * k;
+        I.partials = b->partials + (size_t)k * 2 * pstride * kPartialStride;
+        I.pstride = pstride;
+    }
+    if (!nimg.empty()) {
+        int64_t off = 0;
+        for (auto &im : nimg) {
+            im.tmp = b->ntmp + off;
+            off += (int64_t)im.g.rows * im.g.cols;
+            ntile_start.push_back(ntile_start.back() + normal_tiles(im.g));
+        }
+        b->n_nimg = (int)nimg.size();
+        b->total_ntiles = ntile_start.back();
+        alloc((void **)&b->d_ntile_start, ntile_start.size() * sizeof(int));
+    }
+    if (e == hipSuccess) e = hipMemcpy(b->d_inst, hi.data(), n * sizeof(Inst), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_pre_start, pre_start.data(), pre_start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->state, 0, (size_t)n * 2 * sizeof(RegState));
+    if (e == hipSuccess && !nimg.empty()) {
+        e = hipMemcpy(b->d_nimg, nimg.data(), nimg.size() * sizeof(NormImg), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_ntile_start, ntile_start.data(), ntile_start.size() * sizeof(int),
+                          hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_batch(b);
+        set_error(std::string("batch upload failed: ") + hipGetErrorString(e));
+        return UPS_ERR_HIP;
+    }
+    *out = b;
+    return UPS_OK;
+}
+
+void ups_batch_destroy(ups_batch *b) {
+    if (!b) return;
+    Guard dg(b->device);
+    free_batch(b);
+}
+
+ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]) {
+    UPS_REQUIRE(b && out, "null argument");
+    for (int l = 0; l < 4; l++) out[l] = b->K[l];
+    return UPS_OK;
+}
+
+ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_params *p, void *stream) {
+    UPS_REQUIRE(ctx && b && p, "null argument");
+    UPS_REQUIRE(p->atrous_levels >= 1 && p->atrous_levels <= 3, "batched normals need atrous_levels in [1, 3]");
+    UPS_REQUIRE(p->sigma_n > 0.f && p->sigma_r > 0.f && p->max_rel_jump >= 0.f, "sigmas must be > 0");
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    if (b->n_nimg == 0) return UPS_OK;
+    return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p, (hipStream_t)stream);
+}
+
+ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d,
+                              void *stream) {
+    UPS_REQUIRE(ctx && b, "null argument");
+    ups_status st;
+    if ((st = check_ptr(init_d, 8, "init poses")) != UPS_OK) return st;
+    if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    hipStream_t s = (hipStream_t)stream;
+    const ups_icp_params &p = b->p;
+    const int n = b->n;
+    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, s)) != UPS_OK)
+        return st;
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cos_theta = p.cos_theta_max;
+    a.min_inliers = p.min_inliers;
+    a.stop_norm = p.stop_update_norm;
+    a.prev_level = -1;
+    // (level, iteration) sequence of the Gauss-Newton launches
+    std::vector<int> seq;
+    for (int l = p.levels - 1; l >= 0; l--)
+        for (int it = 0; it < p.iters[l]; it++) seq.push_back(l);
+    for (size_t q = 0; q < seq.size(); q++) {
+        const int l = seq[q];
+        a.level = l;
+        a.d_max2 = p.d_max[l] * p.d_max[l];
+        if ((st = launch_icp_batch(b->K[l], p.precision, MODE_ITER, b->d_inst, b->d_tile_start + l * (n + 1), n,
+                                   a, b->total_tiles[l], s)) != UPS_OK)
+            return st;
+        StepArgs sa = a;
+        sa.prev_level = l;
+        sa.first_of_level = (q + 1 < seq.size() && seq[q + 1] != l);
+        sa.check_max_iters = (q + 1 == seq.size() && l == 0 && p.stop_update_norm > 0.0);
+        if ((st = launch_solve_batch(p.precision, b->d_inst, n, sa, s)) != UPS_OK) return st;
+    }
+    a.level = 0;
+    a.d_max2 = p.d_max[0] * p.d_max[0];
+    a.tau2 = a.d_max2;
+    if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0],
+                               s)) != UPS_OK)
+        return st;
+    return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
+}
+
+}  // extern "C"

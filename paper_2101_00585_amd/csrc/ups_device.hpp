@@ -21,9 +21,35 @@ struct DGeom {
     int stride;           // 2^level into the level-0 ray tables
     float el_top, inv_d_el, az_scale;  // az_scale = cols / (2 pi)
     float r_min, r_max;
+    int narrow;             // every row (with half a row of margin) lies within +-45 deg elevation
     const float2 *lut_row;  // [rows0] (cos el, sin el)
     const float2 *lut_col;  // [cols0] (cos az, sin az)
 };
+
+// Loads through explicit address spaces.  Pointers that reach a kernel inside
+// a descriptor in memory are generic to the compiler, which would emit flat
+// loads (counted on both the vector-memory and the LDS counters); these
+// helpers issue global loads, and scalar loads for wave-uniform read-only
+// tables.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+#define UPS_AS_GLOBAL __attribute__((address_space(1)))
+#define UPS_AS_CONST __attribute__((address_space(4)))
+
+__device__ __forceinline__ float4 ldg(const float4 *p, int idx) {
+    const v4f v = ((const UPS_AS_GLOBAL v4f *)p)[idx];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ldg(const float2 *p, int idx) {
+    const v2f v = ((const UPS_AS_GLOBAL v2f *)p)[idx];
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float ldg(const float *p, int idx) { return ((const UPS_AS_GLOBAL float *)p)[idx]; }
+// idx must be the same in every lane of the wavefront
+__device__ __forceinline__ float2 lds_uniform(const float2 *p, int idx) {
+    const v2f v = ((const UPS_AS_CONST v2f *)p)[idx];
+    return make_float2(v.x, v.y);
+}
 
 __device__ __forceinline__ bool range_ok(const DGeom &g, float r) { return r > g.r_min && r <= g.r_max; }
 
@@ -32,9 +58,44 @@ __device__ __forceinline__ bool normal_ok(float4 s) { return s.x != 0.f || s.y !
 __device__ __forceinline__ bool surfel_ok(const DGeom &g, float4 s) { return range_ok(g, s.w) && normal_ok(s); }
 
 __device__ __forceinline__ float3 ray(const DGeom &g, int i, int j) {
-    float2 e = g.lut_row[i * g.stride];
-    float2 a = g.lut_col[j * g.stride];
+    const float2 e = ldg(g.lut_row, i * g.stride);
+    const float2 a = ldg(g.lut_col, j * g.stride);
     return make_float3(e.x * a.x, e.x * a.y, e.y);
+}
+
+// Ray of pixel (i, j) when i is the same in every lane (scalar row-table load).
+__device__ __forceinline__ float3 ray_urow(const DGeom &g, int i, int j) {
+    const float2 e = lds_uniform(g.lut_row, i * g.stride);
+    const float2 a = ldg(g.lut_col, j * g.stride);
+    return make_float3(e.x * a.x, e.x * a.y, e.y);
+}
+
+// atan(a) for |a| <= 1 in FP32 from a minimax polynomial a P(a^2) with the 8
+// coefficients below (fitted for this library by linear programming on the
+// maximum absolute error over [0, 1]: 2.9e-8 rad in exact arithmetic,
+// 1.4e-7 rad when evaluated in FP32).
+__device__ __forceinline__ float atan_unit(float a) {
+    const float s = a * a;
+    float p = -0.004214501939713955f;
+    p = p * s + 0.022454990074038506f;
+    p = p * s - 0.0567864254117012f;
+    p = p * s + 0.09707822650671005f;
+    p = p * s - 0.13935041427612305f;
+    p = p * s + 0.19952043890953064f;
+    p = p * s - 0.33330363035202026f;
+    p = p * s + 0.999999463558197f;
+    return a * p;
+}
+
+// atan2 from atan_unit and the octant symmetries atan(a) = pi/2 - atan(1/a),
+// pi - ..., and the sign of y.  Undefined for x = y = 0 (callers exclude it).
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    float r = atan_unit(mn * __builtin_amdgcn_rcpf(mx));
+    if (ay > ax) r = 1.57079632679489662f - r;
+    if (x < 0.f) r = 3.14159265358979324f - r;
+    return copysignf(r, y);
 }
 
 // Nearest pixel centre of the direction of q: i = floor(fi + 1/2),
@@ -44,8 +105,15 @@ __device__ __forceinline__ float3 ray(const DGeom &g, int i, int j) {
 __device__ __forceinline__ bool project(const DGeom &g, float3 q, int &pi, int &pj) {
     float rho = sqrtf(q.x * q.x + q.y * q.y);
     if (rho == 0.f && q.z == 0.f) return false;
-    float el = atan2f(q.z, rho);
-    float az = atan2f(q.y, q.x);
+    float el;
+    if (g.narrow) {
+        // the panorama lies within +-45 deg: steeper directions have no pixel
+        if (!(fabsf(q.z) < rho)) return false;
+        el = atan_unit(q.z * __builtin_amdgcn_rcpf(rho));
+    } else {
+        el = atan2_fast(q.z, rho);
+    }
+    float az = atan2_fast(q.y, q.x);
     if (az < 0.f) az += kTwoPi;
     float fi = floorf((g.el_top - el) * g.inv_d_el + 0.5f);
     if (!(fi >= 0.f && fi < (float)g.rows)) return false;
@@ -90,6 +158,58 @@ __device__ __forceinline__ float3 sub3(float3 a, float3 b) { return make_float3(
 
 __device__ __forceinline__ float3 xyz(float4 s) { return make_float3(s.x, s.y, s.z); }
 
+// The association split in two phases so that a caller can overlap the
+// keyframe gathers of one pixel with the scan loads of the next:
+//   scan_side: transform the scan point and normal, project into the keyframe
+//              and issue the keyframe loads (surfel and ray tables);
+//   kf_side:   the Omega filter and the residual once those loads arrived.
+struct Gather {
+    float3 q, m;  // transformed point and normal
+    int kf_index; // -1: no scan surfel or no keyframe pixel
+    float4 s1;    // keyframe surfel
+    float2 e, a;  // keyframe ray tables (cos, sin) of the row and the column
+};
+
+__device__ __forceinline__ Gather scan_side(const DGeom &sg, float4 s2, float2 e, float2 ca, const DGeom &kg,
+                                            const float4 *__restrict__ kf, const Rt32 &T) {
+    Gather G;
+    G.kf_index = -1;
+    if (!surfel_ok(sg, s2)) return G;
+    const float3 u = make_float3(e.x * ca.x, e.x * ca.y, e.y);
+    const float3 p = make_float3(s2.w * u.x, s2.w * u.y, s2.w * u.z);
+    G.q = transform(T, p);
+    G.m = rotate(T, make_float3(s2.x, s2.y, s2.z));
+    int ki, kj;
+    if (!project(kg, G.q, ki, kj)) return G;
+    G.kf_index = ki * kg.cols + kj;
+    G.s1 = ldg(kf, G.kf_index);
+    G.e = ldg(kg.lut_row, ki * kg.stride);
+    G.a = ldg(kg.lut_col, kj * kg.stride);
+    return G;
+}
+
+__device__ __forceinline__ void kf_side(const DGeom &kg, const Gather &G, float d_max2, float cos_theta_max,
+                                        bool &inlier, float &r, float3 &n1) {
+    inlier = false;
+    r = 0.f;
+    n1 = make_float3(0.f, 0.f, 0.f);
+    if (G.kf_index < 0 || !surfel_ok(kg, G.s1)) return;
+    float3 d;
+    {
+        // no FMA contraction: q - s1 must vanish exactly when the pose is the
+        // identity and q, s1 are the same pixel's point
+#pragma clang fp contract(off)
+        const float3 uk = make_float3(G.e.x * G.a.x, G.e.x * G.a.y, G.e.y);
+        const float3 x1 = make_float3(G.s1.w * uk.x, G.s1.w * uk.y, G.s1.w * uk.z);
+        d = sub3(G.q, x1);
+    }
+    n1 = make_float3(G.s1.x, G.s1.y, G.s1.z);
+    if (!(dot3(d, d) <= d_max2)) return;
+    if (!(dot3(G.m, n1) >= cos_theta_max)) return;
+    inlier = true;
+    r = dot3(d, n1);
+}
+
 // One projective correspondence of Equation 1 (Section III-B).
 struct Pair {
     int kf_index;  // -1 when the scan pixel has no surfel or projects outside
@@ -98,29 +218,33 @@ struct Pair {
     float3 q, n1;  // J = [q x n1, n1]
 };
 
+template <bool UNIFORM_ROW = false>
 __device__ __forceinline__ Pair associate(const DGeom &sg, float4 s2, int i, int j, const DGeom &kg,
                                           const float4 *__restrict__ kf, const Rt32 &T, float d_max2,
                                           float cos_theta_max) {
-    // no FMA contraction here: q - s1 must vanish exactly when the pose is the
-    // identity and q, s1 are the same pixel's point
-#pragma clang fp contract(off)
     Pair pr;
     pr.kf_index = -1;
     pr.inlier = false;
     pr.r = 0.f;
     if (!surfel_ok(sg, s2)) return pr;
-    float3 u = ray(sg, i, j);
+    float3 u = UNIFORM_ROW ? ray_urow(sg, i, j) : ray(sg, i, j);
     float3 p = make_float3(s2.w * u.x, s2.w * u.y, s2.w * u.z);
     float3 q = transform(T, p);
     float3 m = rotate(T, xyz(s2));
     int ki, kj;
     if (!project(kg, q, ki, kj)) return pr;
     pr.kf_index = ki * kg.cols + kj;
-    float4 s1 = kf[pr.kf_index];
+    float4 s1 = ldg(kf, pr.kf_index);
     if (!surfel_ok(kg, s1)) return pr;
     float3 uk = ray(kg, ki, kj);
-    float3 x1 = make_float3(s1.w * uk.x, s1.w * uk.y, s1.w * uk.z);
-    float3 d = sub3(q, x1);
+    float3 d;
+    {
+        // no FMA contraction: q - s1 must vanish exactly when the pose is the
+        // identity and q, s1 are the same pixel's point
+#pragma clang fp contract(off)
+        const float3 x1 = make_float3(s1.w * uk.x, s1.w * uk.y, s1.w * uk.z);
+        d = sub3(q, x1);
+    }
     float3 n1 = xyz(s1);
     if (!(dot3(d, d) <= d_max2)) return pr;
     if (!(dot3(m, n1) >= cos_theta_max)) return pr;

@@ -67,6 +67,91 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
     s = t;
 }
 
+// Per-thread accumulation of the per-pixel terms in the three precision modes.
+template <int PREC, int NV>
+struct ThreadAcc;
+
+// Compensated FP32 where it pays: the Gauss-Newton fixed point is where
+// J^T r vanishes, so J^T r (values 21..26), sum r^2 (27) and the truncated
+// cost (30) are Kahan-compensated; the 21 J^T J entries, whose rounding only
+// perturbs the step size, are plain FP32 sums; counts are exact.
+template <int NV>
+struct ThreadAcc<UPS_PREC_KAHAN_F64, NV> {
+    float s[NV], c[8];
+    static __device__ __forceinline__ constexpr int comp(int v) { return (v >= 21 && v < 28) ? v - 21 : (v == 30 ? 7 : -1); }
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int v = 0; v < NV; v++) s[v] = 0.f;
+#pragma unroll
+        for (int v = 0; v < 8; v++) c[v] = 0.f;
+    }
+    __device__ __forceinline__ void add(int v, float x) {
+        if (comp(v) >= 0) kahan_add(s[v], c[comp(v)], x);
+        else s[v] += x;
+    }
+    __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
+    __device__ __forceinline__ double get(int v) const {
+        return comp(v) >= 0 ? (double)s[v] - (double)c[comp(v)] : (double)s[v];
+    }
+};
+
+template <int NV>
+struct ThreadAcc<UPS_PREC_F32, NV> {  // plain FP32
+    float s[NV];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int v = 0; v < NV; v++) s[v] = 0.f;
+    }
+    __device__ __forceinline__ void add(int v, float x) { s[v] += x; }
+    __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
+    __device__ __forceinline__ float get(int v) const { return s[v]; }
+};
+
+template <int NV>
+struct ThreadAcc<UPS_PREC_F64, NV> {  // FP64 (callers add exact FP64 products)
+    double s[NV];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int v = 0; v < NV; v++) s[v] = 0.0;
+    }
+    __device__ __forceinline__ void add(int v, double x) { s[v] += x; }
+    __device__ __forceinline__ void fma(int v, double a, double b) { s[v] = ::fma(a, b, s[v]); }
+    __device__ __forceinline__ void count(int v) { s[v] += 1.0; }
+    __device__ __forceinline__ double get(int v) const { return s[v]; }
+};
+
+template <int PREC>
+using AccOf = typename std::conditional<PREC == UPS_PREC_F32, float, double>::type;
+
+// Add one inlier's 28 terms: the upper triangle of J^T J, J^T r and r^2.
+template <int PREC, int NV>
+__device__ __forceinline__ void add_terms(ThreadAcc<PREC, NV> &acc, const Pair &pr) {
+    const float3 qn = cross3(pr.q, pr.n1);
+    if constexpr (PREC == UPS_PREC_F64) {
+        const double J[6] = {qn.x, qn.y, qn.z, pr.n1.x, pr.n1.y, pr.n1.z};
+        const double r = pr.r;
+        int e = 0;
+#pragma unroll
+        for (int u = 0; u < 6; u++)
+#pragma unroll
+            for (int w = u; w < 6; w++) acc.fma(e++, J[u], J[w]);
+#pragma unroll
+        for (int u = 0; u < 6; u++) acc.fma(21 + u, J[u], r);
+        acc.fma(27, r, r);
+    } else {
+        const float J[6] = {qn.x, qn.y, qn.z, pr.n1.x, pr.n1.y, pr.n1.z};
+        int e = 0;
+#pragma unroll
+        for (int u = 0; u < 6; u++)
+#pragma unroll
+            for (int w = u; w < 6; w++) acc.add(e++, J[u] * J[w]);
+#pragma unroll
+        for (int u = 0; u < 6; u++) acc.add(21 + u, J[u] * pr.r);
+        acc.add(27, pr.r * pr.r);
+    }
+    acc.count(28);
+}
+
 // Sum NV per-thread values over the 256-thread block in a fixed order: DPP row
 // sums, then the 16 row sums of each value added in row order.  tot[v] holds
 // the block total of value v for every thread after the call.
@@ -213,6 +298,7 @@ __device__ void gn_step(const StepArgs &a, const T *tot, RegState &S) {
     }
     exp_compose<T>(xi, S.R, S.t);
     S.iters_run += 1;
+    S.level_iters[a.prev_level] += 1;
     T nrm = 0;
     for (int k = 0; k < 6; k++) nrm += xi[k] * xi[k];
     S.last_norm = (double)sqrt(nrm);
@@ -225,16 +311,20 @@ __device__ void gn_step(const StepArgs &a, const T *tot, RegState &S) {
 // block, or a single folded one when there are more than 256.
 __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
 
-template <int K, int PREC, int MODE>
+// FUSED: the block first applies the previous launch's update itself (step 0
+// above; single registrations).  Otherwise (batches) a separate one-block-per-
+// registration launch has already applied it and left the pose, and whether
+// this launch has work for the registration, in state slot 0.
+template <int K, int PREC, int MODE, bool FUSED>
 __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
     constexpr int NV = (MODE == MODE_ITER) ? 29 : 31;  // EVAL adds valid count and truncated cost
-    using Acc = typename std::conditional<PREC == UPS_PREC_KAHAN_F64, double, float>::type;
+    using Acc = AccOf<PREC>;
     const int tid = threadIdx.x;
     const int l = a.level;
     const int ntiles = I.nblocks[l];
-    RegState *slot_in = I.state + a.parity, *slot_out = I.state + (a.parity ^ 1);
+    RegState *slot_in = I.state + (FUSED ? a.parity : 0), *slot_out = I.state + (a.parity ^ 1);
     const double *part_in = I.partials + (size_t)a.parity * I.pstride * kPartialStride;
-    double *part_out = I.partials + (size_t)(a.parity ^ 1) * I.pstride * kPartialStride;
+    double *part_out = I.partials + (size_t)(FUSED ? (a.parity ^ 1) : 0) * I.pstride * kPartialStride;
 
     __shared__ RegState S;
     __shared__ Acc rows[31][16];
@@ -246,80 +336,86 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     const int npix = sg.rows * sg.cols;
     const int base = tile * (kBlock * K);
 
-    // ---- issue the independent loads together: this launch's scan surfels,
-    // the previous launch's block partials and the state
-    float4 s2[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int p = base + k * kBlock + tid;
-        s2[k] = p < npix ? scan[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+    // ---- issue the independent loads together: the first scan surfel and
+    // its ray-table column, the previous launch's block partials and the state.
+    // Scan loads are clamped into the image (the last wavefronts of a tile may
+    // run past it) and masked afterwards, so no load sits behind a branch.
+    const int pw0 = __builtin_amdgcn_readfirstlane(base + (tid & ~63));
+    // column of this thread's pixel; it advances by kBlock mod cols per pixel
+    const int col_step = kBlock % sg.cols;
+    int jn = (base + tid) % sg.cols;
+    float4 nxt = ldg(scan, min(base + tid, npix - 1));
+    float2 nxt_a = ldg(sg.lut_col, jn * sg.stride);
+    if (!FUSED) {
+        if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
+        if (tid == 0) S = *slot_in;
+        __syncthreads();
+    } else {
+        Acc px[29];
+        load_partials<29, Acc>(part_in, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0, px);
+        if (tid == 0) S = *slot_in;
+        __syncthreads();
+        // ---- 0. the previous launch's update, solved identically by every block
+        if (S.pending && !S.stop) {
+            block_reduce<29, Acc>(px, rows, tot);
+            if (tid == 0) gn_step<Acc>(a, tot, S);
+        }
+        if (tid == 0) {
+            S.pending = 0;
+            if (MODE == MODE_ITER && a.first_of_level) S.level_active = 1;
+            if (MODE == MODE_EVAL && a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
+            active = (MODE == MODE_EVAL) || (!S.stop && S.level_active);
+        }
+        __syncthreads();
+        if (!active) {
+            if (tile == 0 && tid == 0) *slot_out = S;
+            return;
+        }
     }
-    Acc px[29];
-    load_partials<29, Acc>(part_in, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0, px);
-    if (tid == 0) S = *slot_in;
-    __syncthreads();
 
-    // ---- 0. the previous launch's update, solved identically by every block
-    if (S.pending && !S.stop) {
-        block_reduce<29, Acc>(px, rows, tot);
-        if (tid == 0) gn_step<Acc>(a, tot, S);
-    }
-    if (tid == 0) {
-        S.pending = 0;
-        if (MODE == MODE_ITER && a.first_of_level) S.level_active = 1;
-        if (MODE == MODE_EVAL && a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
-        active = (MODE == MODE_EVAL) || (!S.stop && S.level_active);
-    }
-    __syncthreads();
-    if (!active) {
-        if (tile == 0 && tid == 0) *slot_out = S;
-        return;
-    }
-
-    // ---- 1. association of K pixels per thread at the updated pose
+    // ---- 1. association of K pixels per thread at the updated pose (the pose
+    // is block-uniform: kept in scalar registers)
     Rt32 T;
 #pragma unroll
-    for (int k = 0; k < 9; k++) T.r[k] = (float)S.R[k];
+    for (int k = 0; k < 9; k++) T.r[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.R[k])));
 #pragma unroll
-    for (int k = 0; k < 3; k++) T.t[k] = (float)S.t[k];
-    float s[NV], c[NV];
-#pragma unroll
-    for (int v = 0; v < NV; v++) s[v] = c[v] = 0.f;
-#pragma unroll
+    for (int k = 0; k < 3; k++) T.t[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.t[k])));
+    ThreadAcc<PREC, NV> acc;
+    acc.zero();
+    int pw = pw0;
+#pragma unroll 2
     for (int k = 0; k < K; k++) {
         // the 64 pixels of a wavefront lie in one row (cols is a multiple of 64)
-        const int pw = __builtin_amdgcn_readfirstlane(base + k * kBlock + (tid & ~63));
         if (pw >= npix) break;
+        const float4 s2 = (base + k * kBlock + tid < npix) ? nxt : make_float4(0.f, 0.f, 0.f, 0.f);
         const int i = pw / sg.cols;
-        const int j = base + k * kBlock + tid - i * sg.cols;
-        const Pair pr = associate(sg, s2[k], i, j, kg, kf, T, a.d_max2, a.cos_theta);
-        if (pr.inlier) {
-            const float3 qn = cross3(pr.q, pr.n1);
-            const float J[6] = {qn.x, qn.y, qn.z, pr.n1.x, pr.n1.y, pr.n1.z};
-            int e = 0;
-#pragma unroll
-            for (int u = 0; u < 6; u++)
-#pragma unroll
-                for (int w = u; w < 6; w++) {
-                    if (PREC == UPS_PREC_KAHAN_F64) kahan_add(s[e], c[e], J[u] * J[w]);
-                    else s[e] += J[u] * J[w];
-                    e++;
-                }
-#pragma unroll
-            for (int u = 0; u < 6; u++) {
-                if (PREC == UPS_PREC_KAHAN_F64) kahan_add(s[21 + u], c[21 + u], J[u] * pr.r);
-                else s[21 + u] += J[u] * pr.r;
-            }
-            if (PREC == UPS_PREC_KAHAN_F64) kahan_add(s[27], c[27], pr.r * pr.r);
-            else s[27] += pr.r * pr.r;
-            s[28] += 1.f;
+        const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
+        const Gather G = scan_side(sg, s2, e, nxt_a, kg, kf, T);
+        // next pixel's scan loads go out behind this pixel's keyframe gathers
+        pw = __builtin_amdgcn_readfirstlane(pw + kBlock);
+        if (k + 1 < K) {
+            const int pn = base + (k + 1) * kBlock + tid;
+            jn += col_step;
+            jn = jn >= sg.cols ? jn - sg.cols : jn;
+            nxt = ldg(scan, min(pn, npix - 1));
+            nxt_a = ldg(sg.lut_col, jn * sg.stride);
+        }
+        bool inl;
+        float r;
+        float3 n1;
+        kf_side(kg, G, a.d_max2, a.cos_theta, inl, r, n1);
+        if (inl) {
+            Pair pr;
+            pr.inlier = true;
+            pr.r = r;
+            pr.q = G.q;
+            pr.n1 = n1;
+            add_terms<PREC, NV>(acc, pr);
         }
         if (MODE == MODE_EVAL) {
-            if (range_ok(sg, s2[k].w)) {
-                s[29] += 1.f;
-                const float t = pr.inlier ? fminf(pr.r * pr.r, a.tau2) : a.tau2;
-                if (PREC == UPS_PREC_KAHAN_F64) kahan_add(s[30], c[30], t);
-                else s[30] += t;
+            if (range_ok(sg, s2.w)) {
+                acc.count(29);
+                acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
             }
         }
     }
@@ -328,11 +424,11 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     {
         Acc x[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) x[v] = (PREC == UPS_PREC_KAHAN_F64) ? (Acc)s[v] - (Acc)c[v] : (Acc)s[v];
+        for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
         block_reduce<NV, Acc>(x, rows, tot);
     }
     if (tid < NV) part_out[(size_t)tile * kPartialStride + tid] = (double)tot[tid];
-    if (tile == 0 && tid == 0) {
+    if (FUSED && tile == 0 && tid == 0) {
         S.pending = (MODE == MODE_ITER);
         S.npartials = ntiles;
         *slot_out = S;
@@ -341,7 +437,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
 
 template <int K, int PREC, int MODE>
 __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
-    icp_block<K, PREC, MODE>(I, a, blockIdx.x);
+    icp_block<K, PREC, MODE, true>(I, a, blockIdx.x);
 }
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix
@@ -356,15 +452,41 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ i
         if (tile_start[mid] <= b) lo = mid;
         else hi = mid;
     }
-    icp_block<K, PREC, MODE>(insts[lo], a, b - tile_start[lo]);
+    icp_block<K, PREC, MODE, false>(insts[lo], a, b - tile_start[lo]);
+}
+
+// Batch, between two Gauss-Newton launches: one block per registration
+// reduces the partials of the launch that just ran (if it processed the
+// registration), applies the update, and decides whether the next launch
+// processes the registration.  a.prev_level: level of that launch;
+// a.first_of_level: the next launch starts a new level; a.check_max_iters: it
+// was the last launch of level 0.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_solve_batch(const Inst *__restrict__ insts, StepArgs a) {
+    using Acc = AccOf<PREC>;
+    __shared__ RegState S;
+    __shared__ Acc rows[29][16];
+    __shared__ Acc tot[32];
+    const Inst &I = insts[blockIdx.x];
+    if (threadIdx.x == 0) S = I.state[0];
+    __syncthreads();
+    if (S.active && !S.stop) {
+        reduce_partials<29, Acc>(I.partials, npartials_of(I.nblocks[a.prev_level]), rows, tot);
+        if (threadIdx.x == 0) gn_step<Acc>(a, tot, S);
+    }
+    if (threadIdx.x != 0) return;
+    if (a.first_of_level) S.level_active = 1;
+    if (a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
+    S.active = !S.stop && S.level_active;
+    I.state[0] = S;
 }
 
 // One block: the evaluation partials -> result (quality at the final pose,
 // plus the state's pose, status, iteration count and last step norm), or ->
 // normal equations.
 template <int PREC>
-__device__ __forceinline__ void finish_block(const Inst &I, int parity) {
-    using Acc = typename std::conditional<PREC == UPS_PREC_KAHAN_F64, double, float>::type;
+__device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_result *res, ups_normal_eq *neq) {
+    using Acc = AccOf<PREC>;
     __shared__ Acc rows[31][16];
     __shared__ Acc tot[32];
     const RegState *S = I.state + parity;
@@ -372,12 +494,13 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity) {
                              rows, tot);
     if (threadIdx.x != 0) return;
     const double n_in = (double)tot[28], n_valid = (double)tot[29];
-    if (I.res) {
-        ups_icp_result *r = I.res;
+    if (res) {
+        ups_icp_result *r = res;
         for (int k = 0; k < 9; k++) r->T.R[k] = S->R[k];
         for (int k = 0; k < 3; k++) r->T.t[k] = S->t[k];
         r->status = S->status;
         r->iters_run = S->iters_run;
+        for (int k = 0; k < 4; k++) r->level_iters[k] = S->level_iters[k];
         r->last_update_norm = S->last_norm;
         for (int k = 0; k < 21; k++) r->JtJ[k] = (double)tot[k];
         for (int k = 0; k < 6; k++) r->Jtr[k] = (double)tot[21 + k];
@@ -387,8 +510,8 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity) {
         r->rms = n_in > 0 ? sqrt((double)tot[27] / n_in) : 0.0;
         r->trunc_cost = (double)tot[30];
     }
-    if (I.neq) {
-        ups_normal_eq *q = I.neq;
+    if (neq) {
+        ups_normal_eq *q = neq;
         for (int k = 0; k < 21; k++) q->JtJ[k] = (double)tot[k];
         for (int k = 0; k < 6; k++) q->Jtr[k] = (double)tot[21 + k];
         q->sum_r2 = (double)tot[27];
@@ -399,19 +522,20 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity) {
 
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_finish_one(Inst I, int parity) {
-    finish_block<PREC>(I, parity);
+    finish_block<PREC>(I, parity, I.res, I.neq);
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict__ insts, int parity) {
-    finish_block<PREC>(insts[blockIdx.x], parity);
+__global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict__ insts, int parity,
+                                                         ups_icp_result *results) {
+    finish_block<PREC>(insts[blockIdx.x], parity, results + blockIdx.x, nullptr);
 }
 
 // More than 256 partials: fold them into one before the next launch reads
 // them (keeps the per-block read of step 0 bounded).
 template <int PREC, int NV>
 __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
-    using Acc = typename std::conditional<PREC == UPS_PREC_KAHAN_F64, double, float>::type;
+    using Acc = AccOf<PREC>;
     __shared__ Acc rows[NV][16];
     __shared__ Acc tot[32];
     RegState *S = I.state + parity;
@@ -455,6 +579,61 @@ __global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *
     }
 }
 
+// Batch: blocks [0, init_blocks) initialise the states from init[k]; the
+// other blocks subsample pyramid pixels, found through the prefix table of
+// per-registration pyramid pixel counts (scan levels, then keyframe levels).
+__global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict__ insts, const ups_pose *init,
+                                                          int n, int levels, int init_blocks,
+                                                          const int *__restrict__ pix_start) {
+    if ((int)blockIdx.x < init_blocks) {
+        const int k = blockIdx.x * kBlock + threadIdx.x;
+        if (k >= n) return;
+        RegState S;
+        memset(&S, 0, sizeof(S));
+        for (int e = 0; e < 9; e++) S.R[e] = init[k].R[e];
+        for (int e = 0; e < 3; e++) S.t[e] = init[k].t[e];
+        S.status = UPS_CONVERGED;
+        S.level_active = 1;
+        S.active = 1;
+        insts[k].state[0] = S;
+        return;
+    }
+    const int t = (blockIdx.x - init_blocks) * kBlock + threadIdx.x;
+    if (t >= pix_start[n]) return;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pix_start[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const Inst &I = insts[lo];
+    int q = t - pix_start[lo];
+    for (int img = 0; img < 2; img++) {
+        const DGeom &g0 = img ? I.kg[0] : I.sg[0];
+        const float4 *src = img ? I.kf[0] : I.scan[0];
+        for (int l = 1; l < levels; l++) {
+            const DGeom &gl = img ? I.kg[l] : I.sg[l];
+            const int npx = gl.rows * gl.cols;
+            if (q < npx) {
+                const int i = q / gl.cols, j = q - i * gl.cols;
+                float4 *dst = const_cast<float4 *>(img ? I.kf[l] : I.scan[l]);
+                dst[q] = src[(size_t)(i << l) * g0.cols + (j << l)];
+                return;
+            }
+            q -= npx;
+        }
+    }
+}
+
+ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
+                                int total_pix, hipStream_t s) {
+    const int ib = (n + kBlock - 1) / kBlock;
+    const int pb = (total_pix + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_prepare_batch, dim3(ib + pb), dim3(kBlock), 0, s, insts, init, n, levels, ib, pix_start);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
 __global__ __launch_bounds__(kBlock) void k_subsample(const float4 *__restrict__ src, int cols0, int level,
                                                       int rows, int cols, float4 *__restrict__ dst) {
     const int q = blockIdx.x * kBlock + threadIdx.x;
@@ -482,95 +661,92 @@ int pick_k_single(int npix) {
     return K;
 }
 
-template <int PREC, int MODE>
-static ups_status launch_one_k(int K, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
-    switch (K) {
-#define UPS_K(k) \
-    case k: hipLaunchKernelGGL((k_icp_one<k, PREC, MODE>), dim3(blocks), dim3(kBlock), 0, s, I, a); break;
-        UPS_K(1) UPS_K(2) UPS_K(4) UPS_K(8) UPS_K(16)
-#undef UPS_K
-        default:
-            set_error("unsupported pixels-per-thread");
-            return UPS_ERR_INVALID_ARG;
+// Compile-time dispatch of (pixels per thread, precision, mode).
+#define UPS_CASE_K(KV, ...)         \
+    case KV: {                      \
+        constexpr int KK = KV;      \
+        __VA_ARGS__;                \
+    } break;
+#define UPS_DISPATCH_K(K, ...)                                                                            \
+    switch (K) {                                                                                          \
+        UPS_CASE_K(1, __VA_ARGS__) UPS_CASE_K(2, __VA_ARGS__) UPS_CASE_K(4, __VA_ARGS__)                  \
+        UPS_CASE_K(8, __VA_ARGS__) UPS_CASE_K(16, __VA_ARGS__) UPS_CASE_K(32, __VA_ARGS__)                \
+        UPS_CASE_K(64, __VA_ARGS__)                                                                       \
+        default:                                                                                          \
+            set_error("unsupported pixels-per-thread");                                                   \
+            return UPS_ERR_INVALID_ARG;                                                                   \
     }
-    UPS_CHECK_HIP(hipGetLastError());
-    return UPS_OK;
+#define UPS_CASE_P(PV, ...)         \
+    case PV: {                      \
+        constexpr int PP = PV;      \
+        __VA_ARGS__;                \
+    } break;
+#define UPS_DISPATCH_P(P, ...)                                                                            \
+    switch (P) {                                                                                          \
+        UPS_CASE_P(UPS_PREC_KAHAN_F64, __VA_ARGS__)                                                       \
+        UPS_CASE_P(UPS_PREC_F32, __VA_ARGS__) UPS_CASE_P(UPS_PREC_F64, __VA_ARGS__)                       \
+        default:                                                                                          \
+            set_error("unknown precision mode");                                                          \
+            return UPS_ERR_INVALID_ARG;                                                                   \
+    }
+
+template <int K, int PREC>
+static void launch_one_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
+    if (mode == MODE_ITER)
+        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+    else
+        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, I, a);
 }
 
 static ups_status launch_one(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
                              hipStream_t s) {
-    if (prec == UPS_PREC_KAHAN_F64)
-        return mode == MODE_ITER ? launch_one_k<UPS_PREC_KAHAN_F64, MODE_ITER>(K, I, a, blocks, s)
-                                 : launch_one_k<UPS_PREC_KAHAN_F64, MODE_EVAL>(K, I, a, blocks, s);
-    return mode == MODE_ITER ? launch_one_k<UPS_PREC_F32, MODE_ITER>(K, I, a, blocks, s)
-                             : launch_one_k<UPS_PREC_F32, MODE_EVAL>(K, I, a, blocks, s);
-}
-
-template <int K, int PREC, int MODE>
-static void launch_batch_t(const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
-                           hipStream_t s) {
-    hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start, n, a);
-}
-
-ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
-                            const StepArgs &a, int blocks, hipStream_t s) {
-    bool ok = true;
-    switch (K * 4 + prec * 2 + mode) {
-#define UPS_B(k)                                                                                         \
-    case k * 4 + UPS_PREC_KAHAN_F64 * 2 + MODE_ITER:                                                     \
-        launch_batch_t<k, UPS_PREC_KAHAN_F64, MODE_ITER>(insts, tile_start, n, a, blocks, s);            \
-        break;                                                                                           \
-    case k * 4 + UPS_PREC_KAHAN_F64 * 2 + MODE_EVAL:                                                     \
-        launch_batch_t<k, UPS_PREC_KAHAN_F64, MODE_EVAL>(insts, tile_start, n, a, blocks, s);            \
-        break;                                                                                           \
-    case k * 4 + UPS_PREC_F32 * 2 + MODE_ITER:                                                           \
-        launch_batch_t<k, UPS_PREC_F32, MODE_ITER>(insts, tile_start, n, a, blocks, s);                  \
-        break;                                                                                           \
-    case k * 4 + UPS_PREC_F32 * 2 + MODE_EVAL:                                                           \
-        launch_batch_t<k, UPS_PREC_F32, MODE_EVAL>(insts, tile_start, n, a, blocks, s);                  \
-        break;
-        UPS_B(1) UPS_B(2) UPS_B(4) UPS_B(8) UPS_B(16)
-#undef UPS_B
-        default:
-            ok = false;
-    }
-    if (!ok) {
-        set_error("unsupported pixels-per-thread / precision");
-        return UPS_ERR_INVALID_ARG;
-    }
+    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_one_t<KK, PP>(mode, I, a, blocks, s)))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
 
-ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, hipStream_t s) {
-    if (prec == UPS_PREC_KAHAN_F64)
-        hipLaunchKernelGGL(k_finish_batch<UPS_PREC_KAHAN_F64>, dim3(n), dim3(kBlock), 0, s, insts, parity);
+template <int K, int PREC>
+static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
+                           hipStream_t s) {
+    if (mode == MODE_ITER)
+        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
+                           n, a);
     else
-        hipLaunchKernelGGL(k_finish_batch<UPS_PREC_F32>, dim3(n), dim3(kBlock), 0, s, insts, parity);
+        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
+                           n, a);
+}
+
+ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
+                            const StepArgs &a, int blocks, hipStream_t s) {
+    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_batch_t<KK, PP>(mode, insts, tile_start, n, a, blocks, s)))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s) {
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_solve_batch<PP>, dim3(n), dim3(kBlock), 0, s, insts, a))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
+                               hipStream_t s) {
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_finish_batch<PP>, dim3(n), dim3(kBlock), 0, s, insts, parity, results))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
 
 static ups_status launch_finish_one(int prec, const Inst &I, int parity, hipStream_t s) {
-    if (prec == UPS_PREC_KAHAN_F64)
-        hipLaunchKernelGGL(k_finish_one<UPS_PREC_KAHAN_F64>, dim3(1), dim3(kBlock), 0, s, I, parity);
-    else
-        hipLaunchKernelGGL(k_finish_one<UPS_PREC_F32>, dim3(1), dim3(kBlock), 0, s, I, parity);
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_finish_one<PP>, dim3(1), dim3(kBlock), 0, s, I, parity))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
 
 static ups_status launch_collapse_one(int prec, int mode, const Inst &I, int parity, hipStream_t s) {
-    if (prec == UPS_PREC_KAHAN_F64) {
-        if (mode == MODE_ITER)
-            hipLaunchKernelGGL((k_collapse_one<UPS_PREC_KAHAN_F64, 29>), dim3(1), dim3(kBlock), 0, s, I, parity);
-        else
-            hipLaunchKernelGGL((k_collapse_one<UPS_PREC_KAHAN_F64, 31>), dim3(1), dim3(kBlock), 0, s, I, parity);
+    if (mode == MODE_ITER) {
+        UPS_DISPATCH_P(prec, hipLaunchKernelGGL((k_collapse_one<PP, 29>), dim3(1), dim3(kBlock), 0, s, I, parity))
     } else {
-        if (mode == MODE_ITER)
-            hipLaunchKernelGGL((k_collapse_one<UPS_PREC_F32, 29>), dim3(1), dim3(kBlock), 0, s, I, parity);
-        else
-            hipLaunchKernelGGL((k_collapse_one<UPS_PREC_F32, 31>), dim3(1), dim3(kBlock), 0, s, I, parity);
+        UPS_DISPATCH_P(prec, hipLaunchKernelGGL((k_collapse_one<PP, 31>), dim3(1), dim3(kBlock), 0, s, I, parity))
     }
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
@@ -664,6 +840,26 @@ __global__ __launch_bounds__(kBlock) void k_correspondences(DGeom sg, const floa
     const Pair pr = associate(sg, scan[p], i, j, kg, kf, T, d_max2, cos_theta);
     idx[p] = pr.kf_index;
     inl[p] = pr.inlier ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_points(DGeom g, const float *__restrict__ xyz, int64_t n,
+                                                           int32_t *ii, int32_t *jj) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const float3 q = make_float3(xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+    int i = -1, j = -1;
+    if (!project(g, q, i, j)) i = j = -1;
+    ii[k] = i;
+    jj[k] = j;
+}
+
+ups_status launch_project_points(const DGeom &g, const float *xyz, int64_t n, int32_t *ii, int32_t *jj,
+                                 hipStream_t s) {
+    if (n == 0) return UPS_OK;
+    hipLaunchKernelGGL(k_project_points, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, xyz, n,
+                       ii, jj);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
 }
 
 ups_status launch_correspondences(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,

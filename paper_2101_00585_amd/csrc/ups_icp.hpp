@@ -17,6 +17,8 @@ struct RegState {
     int level_active;   // 0 once the current level met its stop criterion
     int pending;        // the partials of the previous launch await their update
     int npartials;      // number of those partials
+    int level_iters[4]; // updates applied per level
+    int active;         // batches: the next Gauss-Newton launch processes this registration
 };
 
 // One registration as the kernels see it.
@@ -46,6 +48,11 @@ ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_
                        hipStream_t s);
 ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
                             const StepArgs &a, int blocks, hipStream_t s);
-ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, hipStream_t s);
+ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
+ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
+                               hipStream_t s);
+ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
+                                int total_pix, hipStream_t s);
+__device__ __host__ inline int npartials_host(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
 
 }  // namespace ups

@@ -62,6 +62,7 @@ struct ups_context {
     float2 *lut_arena = nullptr;
     size_t lut_capacity = 0, lut_used = 0;  // in float2
     std::vector<ups::LutEntry> luts;
+    std::vector<std::pair<int64_t, int>> tuned;  // autotuned pixels per thread by panorama size
     std::mutex mu;
 };
 
@@ -73,6 +74,21 @@ constexpr int kPartialStride = 32;  // doubles per block partial
 // (ray tables are uploaded on first use of the geometry).
 ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream_t stream, DGeom *out);
 ups_status check_ptr(const void *p, size_t align, const char *what);
+// Autotuned pixels per thread for batch launches over panoramas of about npix
+// pixels (0 when ups_autotune has not run).
+int autotuned_k(ups_context *ctx, int64_t npix);
+
+// One panorama of a batched normals launch.
+struct NormImg {
+    DGeom g;
+    const float *depth;
+    float4 *out;  // surfel image
+    float4 *tmp;  // a-trous ping-pong buffer of the same size
+};
+
+int normal_tiles(const DGeom &g);
+ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
+                                const ups_normal_params &p, hipStream_t s);
 
 // launchers (each returns UPS_OK or sets the error)
 ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, float4 *surfel,
@@ -81,6 +97,8 @@ ups_status launch_subsample(const DGeom &g0, const float4 *src, int level, float
 ups_status launch_correspondences(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
                                   const ups_pose *T, float d_max, float cos_theta, int32_t *idx, uint8_t *inl,
                                   hipStream_t s);
+ups_status launch_project_points(const DGeom &g, const float *xyz, int64_t n, int32_t *ii, int32_t *jj,
+                                 hipStream_t s);
 ups_status launch_fuse(ups_context *ctx, const DGeom &sg, const float4 *scan, const DGeom &kg, float4 *kf,
                        uint16_t *count, const ups_pose *T, const ups_fuse_params &p, hipStream_t s);
 

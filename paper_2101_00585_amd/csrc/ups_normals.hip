@@ -83,15 +83,15 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
     return o;
 }
 
-// One a-trous level with taps spaced `step`: the block stages the
-// (4 + 4 step) x (64 + 4 step) surfel tile around its 4 x 64 outputs in LDS
-// (rows outside the image empty, columns wrapped), one output per thread.
-__global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__restrict__ in, float4 *__restrict__ out,
-                                                   int step, float inv_sigma_r, float inv_sigma_n2) {
-    extern __shared__ float4 tile[];
+// One a-trous level with taps spaced `step` for the 4 x 64 output tile at
+// (x0, y0): the block stages the (4 + 4 step) x (64 + 4 step) surfel tile
+// around it in LDS (rows outside the image empty, columns wrapped), one output
+// per thread.
+__device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__restrict__ in, float4 *__restrict__ out,
+                                            int x0, int y0, int step, float inv_sigma_r, float inv_sigma_n2,
+                                            float4 *tile) {
     const int halo = 2 * step;
     const int LW = kTileW + 2 * halo, LH = kTileH + 2 * halo;
-    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
     for (int idx = threadIdx.x; idx < LW * LH; idx += kBlock) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = y0 - halo + ly;
@@ -108,6 +108,12 @@ __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__rest
     out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, step, inv_sigma_r, inv_sigma_n2);
 }
 
+__global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__restrict__ in, float4 *__restrict__ out,
+                                                   int step, float inv_sigma_r, float inv_sigma_n2) {
+    extern __shared__ float4 tile[];
+    atrous_tile(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileH, step, inv_sigma_r, inv_sigma_n2, tile);
+}
+
 // Raw normals and the first a-trous level (step 1) in one pass: the block
 // stages the ranges of its 4 x 64 outputs plus a 2-pixel halo (and the
 // neighbour row/column the cross products need), computes the raw normals of
@@ -115,12 +121,11 @@ __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__rest
 constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
 constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
 
-__global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float *__restrict__ depth,
-                                                           float4 *__restrict__ out, float max_rel_jump,
-                                                           float inv_sigma_r, float inv_sigma_n2) {
+__device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float *__restrict__ depth,
+                                                    float4 *__restrict__ out, int x0, int y0, float max_rel_jump,
+                                                    float inv_sigma_r, float inv_sigma_n2) {
     __shared__ float rng[kDH][kDW];
     __shared__ float4 raw[kFH * kFW];
-    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
     // ranges of rows y0-3 .. y0+kTileH+2 and columns x0-2 .. x0+kTileW+2
     for (int idx = threadIdx.x; idx < kDH * kDW; idx += kBlock) {
         const int ly = idx / kDW, lx = idx - ly * kDW;
@@ -152,6 +157,79 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float 
     const int gy = y0 + ty;
     if (gy >= g.rows) return;
     out[gy * g.cols + x0 + tx] = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float *__restrict__ depth,
+                                                           float4 *__restrict__ out, float max_rel_jump,
+                                                           float inv_sigma_r, float inv_sigma_n2) {
+    normals_atrous_tile(g, depth, out, blockIdx.x * kTileW, blockIdx.y * kTileH, max_rel_jump, inv_sigma_r,
+                        inv_sigma_n2);
+}
+
+// ---- batched: block -> (image, tile) through the prefix table of tile counts
+
+__device__ __forceinline__ int find_image(const int *__restrict__ tile_start, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *__restrict__ imgs,
+                                                                 const int *__restrict__ tile_start, int n,
+                                                                 int out_tmp, float max_rel_jump, float inv_sigma_r,
+                                                                 float inv_sigma_n2) {
+    const int k = find_image(tile_start, n, blockIdx.x);
+    const NormImg &im = imgs[k];
+    const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
+    const int by = t / tx, bx = t - by * tx;
+    normals_atrous_tile(im.g, im.depth, out_tmp ? im.tmp : im.out, bx * kTileW, by * kTileH, max_rel_jump,
+                        inv_sigma_r, inv_sigma_n2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restrict__ imgs,
+                                                         const int *__restrict__ tile_start, int n, int src_tmp,
+                                                         int step, float inv_sigma_r, float inv_sigma_n2) {
+    extern __shared__ float4 tile[];
+    const int k = find_image(tile_start, n, blockIdx.x);
+    const NormImg &im = imgs[k];
+    const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
+    const int by = t / tx, bx = t - by * tx;
+    atrous_tile(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW, by * kTileH, step,
+                inv_sigma_r, inv_sigma_n2, tile);
+}
+
+// Tiles of a panorama in the a-trous launches.
+int normal_tiles(const DGeom &g) { return (g.cols / kTileW) * ((g.rows + kTileH - 1) / kTileH); }
+
+ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
+                                const ups_normal_params &p, hipStream_t s) {
+    const int L = p.atrous_levels;
+    const float inv_sr = 1.f / p.sigma_r, inv_sn2 = 1.f / (p.sigma_n * p.sigma_n);
+    if (L == 0 || total_tiles == 0) {
+        if (total_tiles > 0) {
+            set_error("batched normals need at least one a-trous level");
+            return UPS_ERR_UNSUPPORTED;
+        }
+        return UPS_OK;
+    }
+    // ping-pong between out and tmp so that the last level writes out
+    int in_tmp = (L - 1) % 2;
+    hipLaunchKernelGGL(k_normals_atrous_batch, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+                       p.max_rel_jump, inv_sr, inv_sn2);
+    UPS_CHECK_HIP(hipGetLastError());
+    for (int l = 1; l < L; l++) {
+        const int step = 1 << l;
+        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileH + 4 * step) * sizeof(float4);
+        hipLaunchKernelGGL(k_atrous_batch, dim3(total_tiles), dim3(kBlock), lds, s, imgs, tile_start, n, in_tmp, step,
+                           inv_sr, inv_sn2);
+        UPS_CHECK_HIP(hipGetLastError());
+        in_tmp ^= 1;
+    }
+    return UPS_OK;
 }
 
 ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, float4 *surfel,

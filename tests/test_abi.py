@@ -39,7 +39,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(ups.ups_pose) == 96
     assert ctypes.sizeof(ups.ups_geom) == 40
     assert ctypes.sizeof(ups.ups_icp_params) == 4 + 16 + 16 + 4 + 8 + 4 + 4
-    assert ups.RESULT_BYTES == 96 + 24 + 16 + 8 + 21 * 8 + 6 * 8 + 8
+    assert ups.RESULT_BYTES == 96 + 24 + 16 + 8 + 16 + 21 * 8 + 6 * 8 + 8
     assert ups.NEQ_BYTES == 21 * 8 + 6 * 8 + 8 + 16
 
 

@@ -1,0 +1,178 @@
+"""Batched registrations (many uneven panoramas per launch) against the FP64
+oracle, registration by registration, and against the single-registration
+path of the same library.
+
+Inputs follow the batch workload: pairs of rendered panoramas of the box room
+or the outdoor scene, sizes drawn from {64x512, 64x1024, 128x1024, 128x2048},
+motions up to 10 deg / 1 m, 3 pyramid levels with up to 10/10/10 iterations
+and an early exit when the update norm falls below 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BATCH_PARAMS = dict(levels=3, iters=(10, 10, 10), stop_update_norm=1e-6)
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def pairs():
+    # small sizes first so the oracle stays fast; two of each kind
+    sizes = [(64, 512), (64, 1024), (64, 512), (128, 1024), (64, 1024), (64, 512)]
+    return [W.batch_pair(k, size=sz, max_angle=np.radians(6), max_trans=0.5) for k, sz in enumerate(sizes)]
+
+
+@pytest.fixture(scope="module")
+def bctx(gpu_lib):
+    c = gpu_lib.Context(0, max_pixels=128 * 2048, max_batch=512, max_batch_pixels=300 * 128 * 2048)
+    yield c
+    c.close()
+
+
+def _items_from_depth(gpu_lib, pairs):
+    import torch
+    items = []
+    for p in pairs:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g, scan_depth=_t(p["scan"]), kf_depth=_t(p["kf"]),
+                          scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda"),
+                          kf_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda")))
+    return items
+
+
+def test_batch_normals_equal_single(gpu_lib, bctx, pairs):
+    items = _items_from_depth(gpu_lib, pairs)
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    for it in items:
+        g = it["scan_geom"]
+        single = gpu_lib.panorama_normals(bctx, g, it["scan_depth"])
+        assert np.array_equal(_np(single), _np(it["scan_surfel"]))
+        single = gpu_lib.panorama_normals(bctx, g, it["kf_depth"])
+        assert np.array_equal(_np(single), _np(it["kf_surfel"]))
+    b.close()
+
+
+def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs):
+    import torch
+    items, surf = [], []
+    for p in pairs:
+        g = p["geom"]
+        kf = O.panorama_normals(g, p["kf"]).astype(np.float32)
+        scan = O.panorama_normals(g, p["scan"]).astype(np.float32)
+        surf.append((kf, scan))
+        items.append(dict(scan_geom=g, kf_geom=g, scan_surfel=_t(scan), kf_surfel=_t(kf)))
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    res = gpu_lib.read_results(b.register([np.eye(4)] * len(items)))
+    for k, (p, (kf, scan)) in enumerate(zip(pairs, surf)):
+        g = p["geom"]
+        ref = O.register(g, scan, g, kf, np.eye(4), O.IcpParams(**BATCH_PARAMS))
+        rot, tr = synth.pose_error(res[k]["T"], ref["T"])
+        print(f"pair {k} {g.rows}x{g.cols} {p['kind']}: GPU vs oracle {rot:.2e} rad {tr:.2e} m, "
+              f"iters {res[k]['iters_run']} / {ref['iters_run']}, status {res[k]['status']} / {ref['status']}")
+        assert rot < 1e-5 and tr < 1e-5, (k, rot, tr)
+        assert res[k]["status"] == ref["status"]
+        assert abs(res[k]["iters_run"] - ref["iters_run"]) <= 2
+        assert sum(res[k]["level_iters"]) == res[k]["iters_run"]
+        assert abs(res[k]["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
+        # and the registration found the true motion
+        rot_gt, tr_gt = synth.pose_error(res[k]["T"], p["T_gt"])
+        assert rot_gt < 2e-3 and tr_gt < 2e-2, (k, rot_gt, tr_gt)
+    b.close()
+
+
+def test_batch_equals_single_registration(gpu_lib, bctx, pairs):
+    """Batch and single launches differ only in pixels per thread (hence the
+    order of FP32 sums): poses agree far inside the oracle tolerance."""
+    items = []
+    for p in pairs[:3]:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g,
+                          scan_surfel=gpu_lib.panorama_normals(bctx, g, _t(p["scan"])),
+                          kf_surfel=gpu_lib.panorama_normals(bctx, g, _t(p["kf"]))))
+    params = gpu_lib.IcpParams(**BATCH_PARAMS)
+    b = gpu_lib.Batch(bctx, items, params)
+    res = gpu_lib.read_results(b.register([np.eye(4)] * len(items)))
+    for k, it in enumerate(items):
+        g = it["scan_geom"]
+        r1 = gpu_lib.read_result(gpu_lib.register_scan(bctx, g, it["scan_surfel"], g, it["kf_surfel"], np.eye(4),
+                                                       params))
+        rot, tr = synth.pose_error(res[k]["T"], r1["T"])
+        assert rot < 1e-6 and tr < 1e-6, (k, rot, tr)
+        assert res[k]["status"] == r1["status"]
+    b.close()
+
+
+def test_batch_graph_replays_match_eager(gpu_lib, bctx, pairs):
+    """The whole batched call captured in a HIP graph: each of several
+    replays, with eager work in between, reproduces the eager result bitwise."""
+    import torch
+    items = _items_from_depth(gpu_lib, pairs[:4])
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    init = torch.stack([gpu_lib.pose_tensor(np.eye(4)) for _ in items])
+    results = torch.zeros((len(items), gpu_lib.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    b.normals()
+    b.register(init, results)
+    torch.cuda.synchronize()
+    eager = _np(results).copy()
+    s = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        b.normals()
+        b.register(init, results)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=s):
+            b.normals()
+            b.register(init, results)
+    for rep in range(3):
+        results.zero_()
+        # unrelated eager work between replays
+        gpu_lib.panorama_normals(bctx, items[0]["scan_geom"], items[0]["scan_depth"])
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(results), eager), rep
+    b.close()
+
+
+def test_batch_failures_isolated(gpu_lib, bctx, pairs):
+    """An empty registration (no returns) stops with NO_INLIERS without
+    disturbing its neighbours in the batch."""
+    import torch
+    items = _items_from_depth(gpu_lib, pairs[:3])
+    g = items[1]["scan_geom"]
+    items[1]["scan_depth"] = torch.zeros((g.rows, g.cols), dtype=torch.float32, device="cuda")
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    res = gpu_lib.read_results(b.register([np.eye(4)] * 3))
+    assert res[1]["status"] == 3 and res[1]["iters_run"] == 0
+    for k in (0, 2):
+        assert res[k]["status"] in (0, 1)  # converged, or the 1e-6 criterion not met in 10 iterations
+        assert sum(res[k]["level_iters"]) == res[k]["iters_run"] > 0
+        rot, tr = synth.pose_error(res[k]["T"], pairs[k]["T_gt"])
+        assert rot < 2e-3 and tr < 2e-2
+    b.close()
+
+
+def test_autotune_roundtrip(gpu_lib, bctx, tmp_path):
+    path = str(tmp_path / "tune.json")
+    gpu_lib.autotune(bctx, path)
+    txt = open(path).read()
+    assert '"arch": "gfx950' in txt and '"k": ' in txt
+    # a second context loads the cache instead of measuring
+    c2 = gpu_lib.Context(0, max_pixels=1 << 16, max_batch=4, max_batch_pixels=1 << 20)
+    gpu_lib.autotune(c2, path)
+    c2.close()

@@ -148,9 +148,40 @@ def test_correspondences_moved_pose(gpu_lib, ctx, c0, c0_surfels):
     assert oin.sum() > 0.8 * g.rows * g.cols
 
 
+def test_projection_matches_oracle(gpu_lib, ctx):
+    """GPU spherical projection (FP32, own arctangent) against the FP64 oracle
+    on random points: identical pixels except where the exact direction lies
+    within 1e-3 pixel of a pixel boundary, and there it is one of the two
+    neighbours."""
+    import torch
+    for rows, cols in ((64, 512), (128, 2048)):
+        g = lidar_geom(rows, cols)
+        rng = np.random.default_rng(rows)
+        q = rng.normal(size=(200000, 3))
+        q[:, 2] *= 0.3
+        q *= rng.uniform(0.5, 49, size=(len(q), 1))
+        q32 = q.astype(np.float32)
+        gi, gj = gpu_lib.project_points(ctx, g, torch.from_numpy(q32).cuda())
+        gi, gj = _np(gi), _np(gj)
+        oi, oj, ok = O.project(g, q32.astype(np.float64))
+        el = np.arctan2(q32[:, 2].astype(np.float64), np.hypot(q32[:, 0], q32[:, 1]))
+        az = np.arctan2(q32[:, 1].astype(np.float64), q32[:, 0].astype(np.float64)) % (2 * np.pi)
+        fi = (g.el_top - el) / g.d_el
+        fj = az * cols / (2 * np.pi)
+        near = (np.abs(fi - np.floor(fi) - 0.5) < 1e-3) | (np.abs(fj - np.floor(fj) - 0.5) < 1e-3)
+        assert np.array_equal((gi >= 0), ok) or ((gi >= 0) != ok)[~near].sum() == 0
+        same = ok & (gi >= 0) & ~near
+        assert np.array_equal(gi[same], oi[same]) and np.array_equal(gj[same], oj[same])
+        diff = ok & (gi >= 0) & ((gi != oi) | (gj != oj))
+        assert (np.abs(gi[diff] - oi[diff]) <= 1).all()
+        dj = np.abs(gj[diff] - oj[diff])
+        assert (np.minimum(dj, cols - dj) <= 1).all()
+        assert diff.sum() <= near.sum()
+
+
 # --------------------------------------------------------- normal equations
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_normal_equations_fixed_pose(gpu_lib, ctx, c0, c0_surfels, prec):
     kf, scan = c0_surfels
     g = c0["geom"]
@@ -193,6 +224,15 @@ def test_register_config0_matches_oracle(gpu_lib, ctx, c0, c0_surfels):
     assert abs(res["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
     assert res["valid"] == ref["valid"]
     assert abs(res["rms"] - ref["rms"]) < 1e-3 * ref["rms"] + 1e-6
+
+
+def test_register_f64_mode_matches_oracle(gpu_lib, ctx, c0, c0_surfels):
+    kf, scan = c0_surfels
+    g = c0["geom"]
+    res, ref = _register_both(gpu_lib, ctx, g, kf, scan, np.eye(4), gpu_lib.IcpParams(precision=2), O.IcpParams())
+    rot, tr = synth.pose_error(res["T"], ref["T"])
+    print(f"config0 FP64-accumulation vs oracle: {rot:.3e} rad {tr:.3e} m")
+    assert rot < ROT_TOL and tr < TR_TOL
 
 
 def test_register_f32_mode_close(gpu_lib, ctx, c0, c0_surfels):
