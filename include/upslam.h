@@ -257,6 +257,15 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
  * Synchronous; allocates temporary device memory. */
 ups_status ups_autotune(ups_context *ctx, const char *cache_json_path);
 
+/* Time the batch's Gauss-Newton launch at pyramid level `level` alone: marks
+ * every registration active at its current pose, enqueues n_launches
+ * back-to-back launches of that kernel between two HIP events on `stream`, and
+ * returns their average duration in microseconds (synchronises the stream).
+ * Leaves the registration states unusable for anything but a new
+ * ups_register_batch call. */
+ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t level, int32_t n_launches,
+                                    void *stream, float *us_per_launch);
+
 /* Pixels per thread the batch launches use at each pyramid level. */
 ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]);
 

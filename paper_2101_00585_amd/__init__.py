@@ -111,6 +111,7 @@ def load():
         "ups_register_batch": [_P, _P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
+        "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -433,6 +434,14 @@ class Batch:
                                        _dev_ptr(results, torch.uint8, "results"), _stream()))
         results._keep = init
         return results
+
+    def time_iteration(self, level: int = 0, n_launches: int = 20) -> float:
+        """Average microseconds of one Gauss-Newton launch at ``level`` over
+        all registrations (HIP events on the current stream)."""
+        us = ctypes.c_float()
+        _check(_LIB.ups_batch_time_iteration(self.ctx.handle, self._h, int(level), int(n_launches), _stream(),
+                                             ctypes.byref(us)))
+        return us.value
 
     def close(self):
         if getattr(self, "_h", None):

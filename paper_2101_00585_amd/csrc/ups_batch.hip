@@ -147,7 +147,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
             const int np = I.sg[l].rows * I.sg[l].cols;
             I.nblocks[l] = (np + kBlock * b->K[l] - 1) / (kBlock * b->K[l]);
             pstride = std::max(pstride, I.nblocks[l]);
-            if (l > 0) pre += np + I.kg[l].rows * I.kg[l].cols;
+            if (l == 1) pre += np + I.kg[l].rows * I.kg[l].cols;
         }
         pyr_off_s[k] = pyr_total;
         for (int l = 1; l < L; l++) pyr_total += (int64_t)I.sg[l].rows * I.sg[l].cols;
@@ -249,6 +249,44 @@ void ups_batch_destroy(ups_batch *b) {
     if (!b) return;
     Guard dg(b->device);
     free_batch(b);
+}
+
+ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t level, int32_t n_launches, void *stream,
+                                    float *us_per_launch) {
+    UPS_REQUIRE(ctx && b && us_per_launch, "null argument");
+    UPS_REQUIRE(level >= 0 && level < b->p.levels, "level out of range");
+    UPS_REQUIRE(n_launches >= 1 && n_launches <= 10000, "n_launches must be in [1, 10000]");
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    hipStream_t s = (hipStream_t)stream;
+    ups ::StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.level = level;
+    a.prev_level = -1;
+    a.d_max2 = b->p.d_max[level] * b->p.d_max[level];
+    a.cos_theta = b->p.cos_theta_max;
+    a.min_inliers = b->p.min_inliers;
+    ups_status st;
+    if ((st = launch_activate_batch(b->d_inst, b->n, s)) != UPS_OK) return st;
+    hipEvent_t e0, e1;
+    UPS_CHECK_HIP(hipEventCreate(&e0));
+    UPS_CHECK_HIP(hipEventCreate(&e1));
+    st = launch_icp_batch(b->K[level], b->p.precision, MODE_ITER, b->d_inst, b->d_tile_start + level * (b->n + 1),
+                          b->n, a, b->total_tiles[level], s);  // warm-up
+    hipError_t e = hipEventRecord(e0, s);
+    for (int k = 0; k < n_launches && st == UPS_OK && e == hipSuccess; k++)
+        st = launch_icp_batch(b->K[level], b->p.precision, MODE_ITER, b->d_inst,
+                              b->d_tile_start + level * (b->n + 1), b->n, a, b->total_tiles[level], s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != UPS_OK) return st;
+    UPS_CHECK_HIP(e);
+    *us_per_launch = ms * 1000.f / n_launches;
+    return UPS_OK;
 }
 
 ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]) {

@@ -549,6 +549,18 @@ __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
 
 // ------------------------------------------------- pyramid + registration init
 
+// Pyramid of one surfel image from its level-1 pixel q: level-1 pixel (i, j)
+// is level-0 pixel (2i, 2j); when i and j are even it is also level-2 pixel
+// (i/2, j/2), and level-3 pixel (i/4, j/4) when both are multiples of 4.
+__device__ __forceinline__ void pyramid_from_level1(const DGeom *g, const float4 *const *img, int levels, int q) {
+    const int W1 = g[1].cols;
+    const int i = q / W1, j = q - i * W1;
+    const float4 v = ldg(img[0], (2 * i) * g[0].cols + 2 * j);
+    ((float4 *)img[1])[q] = v;
+    if (levels > 2 && ((i | j) & 1) == 0) ((float4 *)img[2])[(i >> 1) * g[2].cols + (j >> 1)] = v;
+    if (levels > 3 && ((i | j) & 3) == 0) ((float4 *)img[3])[(i >> 2) * g[3].cols + (j >> 2)] = v;
+}
+
 __global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *init, int levels) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t == 0) {
@@ -560,28 +572,17 @@ __global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *
         S.level_active = 1;
         I.state[0] = S;
     }
-    // subsample levels 1.. of the scan (image 0) and the keyframe (image 1)
-    int q = t;
-    for (int img = 0; img < 2; img++) {
-        const DGeom &g0 = img ? I.kg[0] : I.sg[0];
-        const float4 *src = img ? I.kf[0] : I.scan[0];
-        for (int l = 1; l < levels; l++) {
-            const DGeom &gl = img ? I.kg[l] : I.sg[l];
-            const int n = gl.rows * gl.cols;
-            if (q < n) {
-                const int i = q / gl.cols, j = q - i * gl.cols;
-                float4 *dst = const_cast<float4 *>(img ? I.kf[l] : I.scan[l]);
-                dst[q] = src[(size_t)(i << l) * g0.cols + (j << l)];
-                return;
-            }
-            q -= n;
-        }
-    }
+    // pyramids of the scan (image 0) and the keyframe (image 1) from their level-1 pixels
+    if (levels < 2) return;
+    const int n0 = I.sg[1].rows * I.sg[1].cols;
+    if (t < n0) pyramid_from_level1(I.sg, I.scan, levels, t);
+    else if (t - n0 < I.kg[1].rows * I.kg[1].cols) pyramid_from_level1(I.kg, I.kf, levels, t - n0);
 }
 
 // Batch: blocks [0, init_blocks) initialise the states from init[k]; the
-// other blocks subsample pyramid pixels, found through the prefix table of
-// per-registration pyramid pixel counts (scan levels, then keyframe levels).
+// other blocks build the pyramids, one thread per level-1 pixel, found
+// through the prefix table of per-registration level-1 pixel counts (scan,
+// then keyframe).
 __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict__ insts, const ups_pose *init,
                                                           int n, int levels, int init_blocks,
                                                           const int *__restrict__ pix_start) {
@@ -607,22 +608,10 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict
         else hi = mid;
     }
     const Inst &I = insts[lo];
-    int q = t - pix_start[lo];
-    for (int img = 0; img < 2; img++) {
-        const DGeom &g0 = img ? I.kg[0] : I.sg[0];
-        const float4 *src = img ? I.kf[0] : I.scan[0];
-        for (int l = 1; l < levels; l++) {
-            const DGeom &gl = img ? I.kg[l] : I.sg[l];
-            const int npx = gl.rows * gl.cols;
-            if (q < npx) {
-                const int i = q / gl.cols, j = q - i * gl.cols;
-                float4 *dst = const_cast<float4 *>(img ? I.kf[l] : I.scan[l]);
-                dst[q] = src[(size_t)(i << l) * g0.cols + (j << l)];
-                return;
-            }
-            q -= npx;
-        }
-    }
+    const int q = t - pix_start[lo];
+    const int n0 = I.sg[1].rows * I.sg[1].cols;
+    if (q < n0) pyramid_from_level1(I.sg, I.scan, levels, q);
+    else pyramid_from_level1(I.kg, I.kf, levels, q - n0);
 }
 
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
@@ -723,6 +712,17 @@ ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const 
     return UPS_OK;
 }
 
+__global__ void k_activate_batch(const Inst *__restrict__ insts, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) insts[k].state[0].active = 1;
+}
+
+ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_activate_batch, dim3((n + 255) / 256), dim3(256), 0, s, insts, n);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s) {
     UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_solve_batch<PP>, dim3(n), dim3(kBlock), 0, s, insts, a))
     UPS_CHECK_HIP(hipGetLastError());
@@ -763,8 +763,7 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
         Ks[l] = pick_k_single(npix);
         I.nblocks[l] = (npix + kBlock * Ks[l] - 1) / (kBlock * Ks[l]);
     }
-    int npre = 0;
-    for (int l = 1; l < p.levels; l++) npre += I.sg[l].rows * I.sg[l].cols + I.kg[l].rows * I.kg[l].cols;
+    const int npre = p.levels > 1 ? I.sg[1].rows * I.sg[1].cols + I.kg[1].rows * I.kg[1].cols : 0;
     const int pre_blocks = npre > 0 ? (npre + kBlock - 1) / kBlock : 1;
     hipLaunchKernelGGL(k_prepare_one, dim3(pre_blocks), dim3(kBlock), 0, s, I, init, p.levels);
     UPS_CHECK_HIP(hipGetLastError());

@@ -48,6 +48,7 @@ ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_
                        hipStream_t s);
 ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
                             const StepArgs &a, int blocks, hipStream_t s);
+ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s);
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
                                hipStream_t s);

@@ -47,16 +47,29 @@ constexpr int kTileW = 64, kTileH = 4;
 
 // One a-trous output from an LDS surfel tile of row pitch LW whose pixel
 // (ly, lx) is the output (ly + 2 step, lx + 2 step) of the tile: 5x5 B3-spline
-// taps spaced `step`, only taps with a normal, weight
-// h[dy] h[dx] exp(-(dr^2 + (2 - 2 n_p.n_q)/sigma_n^2)) with
-// dr = (r_q - r_p)/(sigma_r r_p), renormalised; the range is unchanged.
+// taps spaced `step`, weight h[dy] h[dx] exp(-(dr^2 + (2 - 2 n_p.n_q)/sigma_n^2))
+// with dr = (r_q - r_p)/(sigma_r r_p), renormalised; the range is unchanged.
+// The whole weight is one exp2: log2 e and 1/sigma_n^2 are folded into a
+// scaled copy of the centre normal, sqrt(log2 e)/(sigma_r r_p) into the range
+// difference and log2(h[dy] h[dx]) into the exponent, so a tap costs three
+// FMAs for the normal term, two for the range term and three to accumulate.
+// Taps without a normal need no test: their zero normal adds nothing to the
+// weighted sum, and the sum is renormalised rather than divided by the total
+// weight.
 __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int ly, int lx, int step,
                                                  float inv_sigma_r, float inv_sigma_n2) {
-    const float h[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+    constexpr float kLog2e = 1.4426950408889634f;
+    // log2 of h = (1, 4, 6, 4, 1) / 16
+    constexpr float lh[5] = {-4.f, -2.f, -1.4150374992788437f, -2.f, -4.f};
     const float4 c = tile[(ly + 2 * step) * LW + lx + 2 * step];
     float4 o = make_float4(0.f, 0.f, 0.f, c.w);
     if (!normal_ok(c)) return o;
-    const float inv_rp = inv_sigma_r / c.w;
+    // log2 e (2 - 2 n_p.n_q) / sigma_n^2 = kn - kn n_p.n_q
+    const float kn = 2.f * kLog2e * inv_sigma_n2;
+    const float cx = kn * c.x, cy = kn * c.y, cz = kn * c.z;
+    // log2 e ((r_q - r_p) / (sigma_r r_p))^2 = (r_q sr - r_p sr)^2
+    const float sr = 1.2011224087864498f * inv_sigma_r / c.w;  // sqrt(log2 e) / (sigma_r r_p)
+    const float csr = -c.w * sr;
     float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
     for (int dy = 0; dy < 5; dy++) {
@@ -64,13 +77,15 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
 #pragma unroll
         for (int dx = 0; dx < 5; dx++) {
             const float4 q = row[dx * step];
-            if (!normal_ok(q)) continue;
-            const float dr = (q.w - c.w) * inv_rp;
-            const float dn = 2.f - 2.f * (c.x * q.x + c.y * q.y + c.z * q.z);
-            const float w = h[dy] * h[dx] * __expf(-(dr * dr + dn * inv_sigma_n2));
-            ax += w * q.x;
-            ay += w * q.y;
-            az += w * q.z;
+            float e = fmaf(cx, q.x, lh[dy] + lh[dx] - kn);
+            e = fmaf(cy, q.y, e);
+            e = fmaf(cz, q.z, e);
+            const float d = fmaf(q.w, sr, csr);
+            e = fmaf(-d, d, e);
+            const float w = __builtin_amdgcn_exp2f(e);
+            ax = fmaf(w, q.x, ax);
+            ay = fmaf(w, q.y, ay);
+            az = fmaf(w, q.z, az);
         }
     }
     const float nn = sqrtf(ax * ax + ay * ay + az * az);

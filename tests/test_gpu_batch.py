@@ -66,6 +66,23 @@ def test_batch_normals_equal_single(gpu_lib, bctx, pairs):
     b.close()
 
 
+def test_batch_normals_scans_only(gpu_lib, bctx, pairs):
+    """Items without keyframe depth: only the scans' surfels are written, the
+    resident keyframe surfel images are left as they were."""
+    import torch
+    items = _items_from_depth(gpu_lib, pairs[:4])
+    for it in items:
+        del it["kf_depth"]
+        it["kf_surfel"].fill_(7.0)
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    for it in items:
+        single = gpu_lib.panorama_normals(bctx, it["scan_geom"], it["scan_depth"])
+        assert np.array_equal(_np(single), _np(it["scan_surfel"]))
+        assert bool((it["kf_surfel"] == 7.0).all())
+    b.close()
+
+
 def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs):
     import torch
     items, surf = [], []
