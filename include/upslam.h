@@ -195,6 +195,34 @@ ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const f
                                const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
                                float cos_theta_max, int32_t *kf_index_d, uint8_t *inlier_d, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Precision study: world-frame coordinates.  The keyframe-frame calls above
+ * never form world coordinates, so a keyframe's distance from the world
+ * origin (the 4.4 km drive of Section IV-F) cannot reach
+ * their FP32 arithmetic.  These two variants carry every point in world
+ * coordinates in FP32 instead, given the keyframe's world pose, to measure
+ * what that costs.  Same arguments, layout and errors as their keyframe-frame
+ * counterparts; init, T and the result pose stay scan -> keyframe.
+ * ------------------------------------------------------------------------ */
+
+/* ups_register_scan with the Gauss-Newton state held as the scan's world pose
+ * world_kf_h * T (FP64); per iteration the scan's and the keyframe's world
+ * poses are rounded to FP32, scan points and keyframe surfels are taken to
+ * world coordinates, the scan point is re-expressed in the keyframe frame only
+ * to find its pixel, and the residual r = (q - s1).n1 and J = [q x n1, n1] are
+ * formed from world coordinates (the update is a left perturbation of the
+ * world pose).  world_kf_h: host pointer, finite. */
+ups_status ups_register_scan_world(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                   const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf_h,
+                                   const ups_pose *init_d, const ups_icp_params *p, ups_icp_result *result_d,
+                                   void *stream);
+
+/* ups_correspondences with the association of ups_register_scan_world. */
+ups_status ups_correspondences_world(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                     const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf_h,
+                                     const ups_pose *T_d, float d_max, float cos_theta_max, int32_t *kf_index_d,
+                                     uint8_t *inlier_d, void *stream);
+
 /* Spherical projection (the lookup behind the projective correspondences of
  * Section III-B): for each of n points xyz_d[n][3] (FP32, the panorama's
  * sensor frame) the nearest pixel centre, i_d[k] = row and j_d[k] = column,

@@ -104,6 +104,8 @@ def load():
         "ups_register_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_fuse_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_correspondences": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
+        "ups_register_scan_world": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+        "ups_correspondences_world": [_P, _P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
         "ups_normal_equations": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P, _P],
         "ups_project_points": [_P, _P, _P, ctypes.c_int64, _P, _P, _P],
         "ups_batch_create": [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -289,10 +291,22 @@ def pyramid_level(ctx: Context, geom, surfel, level: int, out=None):
     return out
 
 
+def host_pose(T) -> ups_pose:
+    """Host ups_pose from a 4x4."""
+    T = np.asarray(T, dtype=np.float64)
+    p = ups_pose()
+    for k in range(9):
+        p.R[k] = float(T[k // 3, k % 3])
+    for k in range(3):
+        p.t[k] = float(T[k, 3])
+    return p
+
+
 def register_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, init, params: IcpParams | None = None,
-                  result=None):
+                  result=None, world_kf=None):
     """``init``: a 4x4 (host) or a device FP64 pose tensor.  Returns the device
-    result buffer (``read_result`` decodes it)."""
+    result buffer (``read_result`` decodes it).  ``world_kf``: a 4x4 keyframe
+    world pose selects the world-frame FP32 variant (precision study)."""
     torch = _torch()
     p = (params or IcpParams()).c()
     if result is None:
@@ -302,10 +316,19 @@ def register_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, init
     else:
         init_t = pose_tensor(init, scan_surfel.device)
     sg, kg = geom_c(scan_geom), geom_c(kf_geom)
-    _check(_LIB.ups_register_scan(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan surfel"),
-                                  ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"),
-                                  _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
-                                  _dev_ptr(result, torch.uint8, "result"), _stream()))
+    if world_kf is None:
+        _check(_LIB.ups_register_scan(ctx.handle, ctypes.byref(sg),
+                                      _dev_ptr(scan_surfel, torch.float32, "scan surfel"), ctypes.byref(kg),
+                                      _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"),
+                                      _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
+                                      _dev_ptr(result, torch.uint8, "result"), _stream()))
+    else:
+        w = host_pose(world_kf)
+        _check(_LIB.ups_register_scan_world(ctx.handle, ctypes.byref(sg),
+                                            _dev_ptr(scan_surfel, torch.float32, "scan surfel"), ctypes.byref(kg),
+                                            _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"), ctypes.byref(w),
+                                            _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
+                                            _dev_ptr(result, torch.uint8, "result"), _stream()))
     result._keep_init = init_t  # keep a host-made init alive until the stream consumes it
     return result
 
@@ -329,18 +352,29 @@ def fuse_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, kf_count
 
 
 def correspondences(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T, d_max=0.5,
-                    cos_theta_max=math.cos(math.radians(30.0))):
+                    cos_theta_max=math.cos(math.radians(30.0)), world_kf=None):
+    """(kf_index, inlier) device maps at the pose T; ``world_kf`` (4x4) selects
+    the world-frame FP32 variant."""
     torch = _torch()
     dev = scan_surfel.device
     T_t = T if isinstance(T, torch.Tensor) else pose_tensor(T, dev)
     idx = torch.empty((scan_geom.rows, scan_geom.cols), dtype=torch.int32, device=dev)
     inl = torch.empty((scan_geom.rows, scan_geom.cols), dtype=torch.uint8, device=dev)
     sg, kg = geom_c(scan_geom), geom_c(kf_geom)
-    _check(_LIB.ups_correspondences(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan"),
-                                    ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe"),
-                                    _dev_ptr(T_t, torch.float64, "pose"), float(d_max), float(cos_theta_max),
-                                    _dev_ptr(idx, torch.int32, "kf_index"), _dev_ptr(inl, torch.uint8, "inlier"),
-                                    _stream()))
+    if world_kf is None:
+        _check(_LIB.ups_correspondences(ctx.handle, ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan"),
+                                        ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe"),
+                                        _dev_ptr(T_t, torch.float64, "pose"), float(d_max), float(cos_theta_max),
+                                        _dev_ptr(idx, torch.int32, "kf_index"), _dev_ptr(inl, torch.uint8, "inlier"),
+                                        _stream()))
+    else:
+        w = host_pose(world_kf)
+        _check(_LIB.ups_correspondences_world(ctx.handle, ctypes.byref(sg),
+                                              _dev_ptr(scan_surfel, torch.float32, "scan"), ctypes.byref(kg),
+                                              _dev_ptr(kf_surfel, torch.float32, "keyframe"), ctypes.byref(w),
+                                              _dev_ptr(T_t, torch.float64, "pose"), float(d_max),
+                                              float(cos_theta_max), _dev_ptr(idx, torch.int32, "kf_index"),
+                                              _dev_ptr(inl, torch.uint8, "inlier"), _stream()))
     idx._keep = T_t
     return idx, inl
 

@@ -225,9 +225,11 @@ static ups_status check_levels(const ups_geom *g, int levels, const char *what) 
     return UPS_OK;
 }
 
-ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
-                             const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *init_d,
-                             const ups_icp_params *p, ups_icp_result *result_d, void *stream) {
+// world_kf: null for the keyframe-frame path, else the keyframe's world pose.
+static ups_status register_impl(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf,
+                                const ups_pose *init_d, const ups_icp_params *p, ups_icp_result *result_d,
+                                void *stream) {
     UPS_REQUIRE(ctx, "context is null");
     ups_status st;
     if ((st = check_icp_params(p)) != UPS_OK) return st;
@@ -265,7 +267,34 @@ ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const flo
     I.partials = ctx->partials;
     I.pstride = (int)ctx->max_partial_blocks;
     I.res = result_d;
+    if (world_kf) {
+        I.world = 1;
+        memcpy(I.wR, world_kf->R, sizeof(I.wR));
+        memcpy(I.wt, world_kf->t, sizeof(I.wt));
+    }
     return launch_register(I, init_d, *p, (hipStream_t)stream);
+}
+
+ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                             const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *init_d,
+                             const ups_icp_params *p, ups_icp_result *result_d, void *stream) {
+    return register_impl(ctx, scan_g, scan_surfel_d, kf_g, kf_surfel_d, nullptr, init_d, p, result_d, stream);
+}
+
+static ups_status check_world_pose(const ups_pose *w) {
+    UPS_REQUIRE(w, "world pose is null");
+    for (double v : w->R) UPS_REQUIRE(std::isfinite(v), "world pose is not finite");
+    for (double v : w->t) UPS_REQUIRE(std::isfinite(v), "world pose is not finite");
+    return UPS_OK;
+}
+
+ups_status ups_register_scan_world(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                   const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf_h,
+                                   const ups_pose *init_d, const ups_icp_params *p, ups_icp_result *result_d,
+                                   void *stream) {
+    ups_status st;
+    if ((st = check_world_pose(world_kf_h)) != UPS_OK) return st;
+    return register_impl(ctx, scan_g, scan_surfel_d, kf_g, kf_surfel_d, world_kf_h, init_d, p, result_d, stream);
 }
 
 ups_status ups_fuse_scan(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
@@ -293,9 +322,10 @@ ups_status ups_fuse_scan(ups_context *ctx, const ups_geom *scan_g, const float *
                        (hipStream_t)stream);
 }
 
-ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
-                               const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
-                               float cos_theta_max, int32_t *kf_index_d, uint8_t *inlier_d, void *stream) {
+static ups_status correspondences_impl(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                       const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf,
+                                       const ups_pose *T_d, float d_max, float cos_theta_max, int32_t *kf_index_d,
+                                       uint8_t *inlier_d, void *stream) {
     UPS_REQUIRE(ctx, "context is null");
     ups_status st;
     if ((st = check_ptr(scan_surfel_d, 16, "scan surfel")) != UPS_OK) return st;
@@ -309,8 +339,29 @@ ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const f
     DGeom sg, kg;
     if ((st = device_geom(ctx, scan_g, 0, (hipStream_t)stream, &sg)) != UPS_OK) return st;
     if ((st = device_geom(ctx, kf_g, 0, (hipStream_t)stream, &kg)) != UPS_OK) return st;
+    if (world_kf)
+        return launch_correspondences_world(sg, (const float4 *)scan_surfel_d, kg, (const float4 *)kf_surfel_d, T_d,
+                                            *world_kf, d_max, cos_theta_max, kf_index_d, inlier_d,
+                                            (hipStream_t)stream);
     return launch_correspondences(sg, (const float4 *)scan_surfel_d, kg, (const float4 *)kf_surfel_d, T_d, d_max,
                                   cos_theta_max, kf_index_d, inlier_d, (hipStream_t)stream);
+}
+
+ups_status ups_correspondences(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                               const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *T_d, float d_max,
+                               float cos_theta_max, int32_t *kf_index_d, uint8_t *inlier_d, void *stream) {
+    return correspondences_impl(ctx, scan_g, scan_surfel_d, kf_g, kf_surfel_d, nullptr, T_d, d_max, cos_theta_max,
+                                kf_index_d, inlier_d, stream);
+}
+
+ups_status ups_correspondences_world(ups_context *ctx, const ups_geom *scan_g, const float *scan_surfel_d,
+                                     const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *world_kf_h,
+                                     const ups_pose *T_d, float d_max, float cos_theta_max, int32_t *kf_index_d,
+                                     uint8_t *inlier_d, void *stream) {
+    ups_status st;
+    if ((st = check_world_pose(world_kf_h)) != UPS_OK) return st;
+    return correspondences_impl(ctx, scan_g, scan_surfel_d, kf_g, kf_surfel_d, world_kf_h, T_d, d_max,
+                                cos_theta_max, kf_index_d, inlier_d, stream);
 }
 
 ups_status ups_project_points(ups_context *ctx, const ups_geom *g, const float *xyz_d, int64_t n, int32_t *i_d,

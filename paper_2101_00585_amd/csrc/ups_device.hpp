@@ -210,6 +210,53 @@ __device__ __forceinline__ void kf_side(const DGeom &kg, const Gather &G, float 
     r = dot3(d, n1);
 }
 
+// ---- world-frame variant (precision study): points carried in world
+// coordinates in FP32.  T is the scan's world pose, W the keyframe's; the
+// scan point q = T p is re-expressed in the keyframe frame, W^T (q - W.t), only
+// to find its pixel; the keyframe surfel is taken to the world, s1 = W x1,
+// n1 = W.R n1, and the residual and Jacobian are formed from world
+// coordinates.  At kilometre offsets every world coordinate carries the FP32
+// rounding of its magnitude.
+__device__ __forceinline__ float3 inv_transform(const Rt32 &T, float3 y) {
+    const float3 d = make_float3(y.x - T.t[0], y.y - T.t[1], y.z - T.t[2]);
+    return make_float3(T.r[0] * d.x + T.r[3] * d.y + T.r[6] * d.z, T.r[1] * d.x + T.r[4] * d.y + T.r[7] * d.z,
+                       T.r[2] * d.x + T.r[5] * d.y + T.r[8] * d.z);
+}
+
+__device__ __forceinline__ Gather scan_side_world(const DGeom &sg, float4 s2, float2 e, float2 ca, const DGeom &kg,
+                                                  const float4 *__restrict__ kf, const Rt32 &T, const Rt32 &W) {
+    Gather G;
+    G.kf_index = -1;
+    if (!surfel_ok(sg, s2)) return G;
+    const float3 u = make_float3(e.x * ca.x, e.x * ca.y, e.y);
+    const float3 p = make_float3(s2.w * u.x, s2.w * u.y, s2.w * u.z);
+    G.q = transform(T, p);
+    G.m = rotate(T, make_float3(s2.x, s2.y, s2.z));
+    int ki, kj;
+    if (!project(kg, inv_transform(W, G.q), ki, kj)) return G;
+    G.kf_index = ki * kg.cols + kj;
+    G.s1 = ldg(kf, G.kf_index);
+    G.e = ldg(kg.lut_row, ki * kg.stride);
+    G.a = ldg(kg.lut_col, kj * kg.stride);
+    return G;
+}
+
+__device__ __forceinline__ void kf_side_world(const DGeom &kg, const Gather &G, const Rt32 &W, float d_max2,
+                                              float cos_theta_max, bool &inlier, float &r, float3 &n1) {
+    inlier = false;
+    r = 0.f;
+    n1 = make_float3(0.f, 0.f, 0.f);
+    if (G.kf_index < 0 || !surfel_ok(kg, G.s1)) return;
+    const float3 uk = make_float3(G.e.x * G.a.x, G.e.x * G.a.y, G.e.y);
+    const float3 s1 = transform(W, make_float3(G.s1.w * uk.x, G.s1.w * uk.y, G.s1.w * uk.z));
+    n1 = rotate(W, make_float3(G.s1.x, G.s1.y, G.s1.z));
+    const float3 d = sub3(G.q, s1);
+    if (!(dot3(d, d) <= d_max2)) return;
+    if (!(dot3(G.m, n1) >= cos_theta_max)) return;
+    inlier = true;
+    r = dot3(d, n1);
+}
+
 // One projective correspondence of Equation 1 (Section III-B).
 struct Pair {
     int kf_index;  // -1 when the scan pixel has no surfel or projects outside

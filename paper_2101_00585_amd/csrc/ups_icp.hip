@@ -315,7 +315,8 @@ __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nbloc
 // above; single registrations).  Otherwise (batches) a separate one-block-per-
 // registration launch has already applied it and left the pose, and whether
 // this launch has work for the registration, in state slot 0.
-template <int K, int PREC, int MODE, bool FUSED>
+// WORLD: the world-frame variant (state pose = the scan's world pose).
+template <int K, int PREC, int MODE, bool FUSED, bool WORLD = false>
 __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
     constexpr int NV = (MODE == MODE_ITER) ? 29 : 31;  // EVAL adds valid count and truncated cost
     using Acc = AccOf<PREC>;
@@ -380,6 +381,13 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     for (int k = 0; k < 9; k++) T.r[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.R[k])));
 #pragma unroll
     for (int k = 0; k < 3; k++) T.t[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.t[k])));
+    Rt32 Wk;
+    if constexpr (WORLD) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) Wk.r[k] = (float)I.wR[k];
+#pragma unroll
+        for (int k = 0; k < 3; k++) Wk.t[k] = (float)I.wt[k];
+    }
     ThreadAcc<PREC, NV> acc;
     acc.zero();
     int pw = pw0;
@@ -390,7 +398,9 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
         const float4 s2 = (base + k * kBlock + tid < npix) ? nxt : make_float4(0.f, 0.f, 0.f, 0.f);
         const int i = pw / sg.cols;
         const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
-        const Gather G = scan_side(sg, s2, e, nxt_a, kg, kf, T);
+        Gather G;
+        if constexpr (WORLD) G = scan_side_world(sg, s2, e, nxt_a, kg, kf, T, Wk);
+        else G = scan_side(sg, s2, e, nxt_a, kg, kf, T);
         // next pixel's scan loads go out behind this pixel's keyframe gathers
         pw = __builtin_amdgcn_readfirstlane(pw + kBlock);
         if (k + 1 < K) {
@@ -403,7 +413,8 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
         bool inl;
         float r;
         float3 n1;
-        kf_side(kg, G, a.d_max2, a.cos_theta, inl, r, n1);
+        if constexpr (WORLD) kf_side_world(kg, G, Wk, a.d_max2, a.cos_theta, inl, r, n1);
+        else kf_side(kg, G, a.d_max2, a.cos_theta, inl, r, n1);
         if (inl) {
             Pair pr;
             pr.inlier = true;
@@ -435,9 +446,9 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     }
 }
 
-template <int K, int PREC, int MODE>
+template <int K, int PREC, int MODE, bool WORLD>
 __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
-    icp_block<K, PREC, MODE, true>(I, a, blockIdx.x);
+    icp_block<K, PREC, MODE, true, WORLD>(I, a, blockIdx.x);
 }
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix
@@ -496,8 +507,18 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_
     const double n_in = (double)tot[28], n_valid = (double)tot[29];
     if (res) {
         ups_icp_result *r = res;
-        for (int k = 0; k < 9; k++) r->T.R[k] = S->R[k];
-        for (int k = 0; k < 3; k++) r->T.t[k] = S->t[k];
+        if (I.world) {
+            // scan -> keyframe = (keyframe world pose)^-1 (scan world pose), FP64
+            for (int a = 0; a < 3; a++) {
+                for (int c = 0; c < 3; c++)
+                    r->T.R[3 * a + c] = I.wR[a] * S->R[c] + I.wR[3 + a] * S->R[3 + c] + I.wR[6 + a] * S->R[6 + c];
+                r->T.t[a] = I.wR[a] * (S->t[0] - I.wt[0]) + I.wR[3 + a] * (S->t[1] - I.wt[1]) +
+                            I.wR[6 + a] * (S->t[2] - I.wt[2]);
+            }
+        } else {
+            for (int k = 0; k < 9; k++) r->T.R[k] = S->R[k];
+            for (int k = 0; k < 3; k++) r->T.t[k] = S->t[k];
+        }
         r->status = S->status;
         r->iters_run = S->iters_run;
         for (int k = 0; k < 4; k++) r->level_iters[k] = S->level_iters[k];
@@ -566,8 +587,19 @@ __global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *
     if (t == 0) {
         RegState S;
         memset(&S, 0, sizeof(S));
-        for (int k = 0; k < 9; k++) S.R[k] = init->R[k];
-        for (int k = 0; k < 3; k++) S.t[k] = init->t[k];
+        if (I.world) {
+            // the scan's world pose = keyframe world pose * init, FP64
+            for (int a = 0; a < 3; a++) {
+                for (int c = 0; c < 3; c++)
+                    S.R[3 * a + c] = I.wR[3 * a] * init->R[c] + I.wR[3 * a + 1] * init->R[3 + c] +
+                                     I.wR[3 * a + 2] * init->R[6 + c];
+                S.t[a] = I.wR[3 * a] * init->t[0] + I.wR[3 * a + 1] * init->t[1] + I.wR[3 * a + 2] * init->t[2] +
+                         I.wt[a];
+            }
+        } else {
+            for (int k = 0; k < 9; k++) S.R[k] = init->R[k];
+            for (int k = 0; k < 3; k++) S.t[k] = init->t[k];
+        }
         S.status = UPS_CONVERGED;
         S.level_active = 1;
         I.state[0] = S;
@@ -681,10 +713,17 @@ int pick_k_single(int npix) {
 
 template <int K, int PREC>
 static void launch_one_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
-    if (mode == MODE_ITER)
-        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, I, a);
-    else
-        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+    if (I.world) {
+        if (mode == MODE_ITER)
+            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, true>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+        else
+            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL, true>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+    } else {
+        if (mode == MODE_ITER)
+            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+        else
+            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+    }
 }
 
 static ups_status launch_one(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
@@ -841,6 +880,37 @@ __global__ __launch_bounds__(kBlock) void k_correspondences(DGeom sg, const floa
     inl[p] = pr.inlier ? 1 : 0;
 }
 
+// The world-frame variant at the pose T (scan -> keyframe): the scan's world
+// pose world_kf * T is formed in FP64 and both poses are rounded to FP32, as
+// the world-frame registration does.
+__global__ __launch_bounds__(kBlock) void k_correspondences_world(DGeom sg, const float4 *__restrict__ scan, DGeom kg,
+                                                                  const float4 *__restrict__ kf, const ups_pose *pose,
+                                                                  ups_pose world_kf, float d_max2, float cos_theta,
+                                                                  int32_t *idx, uint8_t *inl) {
+    const int npix = sg.rows * sg.cols;
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= npix) return;
+    Rt32 T, W;
+    for (int a = 0; a < 3; a++) {
+        for (int c = 0; c < 3; c++)
+            T.r[3 * a + c] = (float)(world_kf.R[3 * a] * pose->R[c] + world_kf.R[3 * a + 1] * pose->R[3 + c] +
+                                     world_kf.R[3 * a + 2] * pose->R[6 + c]);
+        T.t[a] = (float)(world_kf.R[3 * a] * pose->t[0] + world_kf.R[3 * a + 1] * pose->t[1] +
+                         world_kf.R[3 * a + 2] * pose->t[2] + world_kf.t[a]);
+    }
+    for (int k = 0; k < 9; k++) W.r[k] = (float)world_kf.R[k];
+    for (int k = 0; k < 3; k++) W.t[k] = (float)world_kf.t[k];
+    const int i = p / sg.cols, j = p - i * sg.cols;
+    const Gather G = scan_side_world(sg, scan[p], ldg(sg.lut_row, i * sg.stride), ldg(sg.lut_col, j * sg.stride), kg,
+                                     kf, T, W);
+    bool in;
+    float r;
+    float3 n1;
+    kf_side_world(kg, G, W, d_max2, cos_theta, in, r, n1);
+    idx[p] = G.kf_index;
+    inl[p] = in ? 1 : 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_project_points(DGeom g, const float *__restrict__ xyz, int64_t n,
                                                            int32_t *ii, int32_t *jj) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -857,6 +927,16 @@ ups_status launch_project_points(const DGeom &g, const float *xyz, int64_t n, in
     if (n == 0) return UPS_OK;
     hipLaunchKernelGGL(k_project_points, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g, xyz, n,
                        ii, jj);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
+                                        const ups_pose *T, const ups_pose &world_kf, float d_max, float cos_theta,
+                                        int32_t *idx, uint8_t *inl, hipStream_t s) {
+    const int npix = sg.rows * sg.cols;
+    hipLaunchKernelGGL(k_correspondences_world, dim3((npix + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sg, scan, kg,
+                       kf, T, world_kf, d_max * d_max, cos_theta, idx, inl);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

@@ -31,6 +31,10 @@ struct Inst {
     int nblocks[4];               // blocks (tiles) per level
     ups_icp_result *res;          // finish target (or null)
     ups_normal_eq *neq;           // finish target (or null)
+    // world-frame variant: the state pose is the scan's world pose, wR/wt the
+    // keyframe's; init and result stay scan -> keyframe
+    int world;
+    double wR[9], wt[3];
 };
 
 // Per-launch arguments.
@@ -44,6 +48,9 @@ struct StepArgs {
 
 int pick_k_single(int npix);
 ups_status launch_register(const Inst &I, const ups_pose *init, const ups_icp_params &p, hipStream_t s);
+ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
+                                        const ups_pose *T, const ups_pose &world_kf, float d_max, float cos_theta,
+                                        int32_t *idx, uint8_t *inl, hipStream_t s);
 ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_theta, int precision,
                        hipStream_t s);
 ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,

@@ -155,3 +155,24 @@ def batch_pair(k: int, base_seed: int = 1000, max_angle=10 * DEG, max_trans=1.0,
 
 def batch(n: int = 256, base_seed: int = 1000, **kw):
     return [batch_pair(k, base_seed, **kw) for k in range(n)]
+
+
+# ----------------------------------------------------------------------------
+# configuration 3: the outdoor sequence far from the world origin
+# ----------------------------------------------------------------------------
+
+def world_offset(seed: int, radius: float = 4400.0, at_rim: bool = False):
+    """A horizontal offset drawn uniformly in a disk of ``radius`` m (on its
+    rim when ``at_rim``), seeded."""
+    rng = np.random.Generator(np.random.PCG64(seed + 4409))
+    a = rng.uniform(0, 2 * math.pi)
+    r = radius if at_rim else radius * math.sqrt(rng.uniform())
+    return (r * math.cos(a), r * math.sin(a))
+
+
+def config3(seed: int = 11, offset=(0.0, 0.0), rows: int = 128, cols: int = 2048, **kw):
+    """Configuration 1 at 128x2048, with the whole scene, path and keyframe
+    placed at a horizontal world offset (metres).  Ray casting and poses are
+    FP64, so the rendered ranges do not depend on the offset beyond FP64
+    rounding; T_world_kf carries it."""
+    return config1(seed=seed, rows=rows, cols=cols, world_offset=offset, **kw)
