@@ -14,9 +14,11 @@
  *     float4 images, and never freed or retained by the library.
  *   - Every call is asynchronous on the given HIP stream (a hipStream_t passed as
  *     void*; NULL = the default stream).  Results land in device memory; the
- *     caller synchronises before reading them.  After ups_context_create no call
- *     allocates device memory, and ups_register_scan / ups_fuse_scan /
- *     ups_panorama_normals / ups_register_batch enqueue only kernels, so they can
+ *     caller synchronises before reading them.  Device memory is allocated only
+ *     by ups_context_create (per-registration scratch), ups_batch_create (a
+ *     batch's scratch) and ups_autotune (its measurement buffers);
+ *     ups_register_scan / ups_fuse_scan / ups_panorama_normals /
+ *     ups_batch_normals / ups_register_batch enqueue only kernels, so they can
  *     be captured into a HIP graph (geometries must have been seen once outside
  *     capture, see ups_context_create).
  *   - One context holds the scratch space of one registration at a time: calls
@@ -152,8 +154,10 @@ typedef struct ups_context ups_context;
 
 /* Create a context on `device` for panoramas of up to max_pixels pixels and
  * batches of up to max_batch registrations whose panoramas total at most
- * max_batch_pixels pixels (scan and keyframe each).  All device memory the
- * library needs is allocated here.  The first use of a new panorama geometry
+ * max_batch_pixels pixels (scan and keyframe each).  The scratch of single
+ * registrations, normals and fusion (pyramids, a-trous buffer, fill keys,
+ * block partials, state, ray tables) is allocated here; a batch allocates its
+ * own in ups_batch_create.  The first use of a new panorama geometry
  * uploads its ray tables synchronously; such a first use is rejected during
  * stream capture (UPS_ERR_INVALID_ARG). */
 ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels, int32_t max_batch,
