@@ -301,6 +301,100 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
 /* Pixels per thread the batch launches use at each pyramid level. */
 ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]);
 
+/* ------------------------------------------------------------------------
+ * Learned pose proposal.  The paper starts loop-closure registrations from a
+ * grid search over candidate transforms (Section III-C); this library can
+ * instead start a registration from the pose a small convolutional network
+ * proposes from the two panoramas, keeping identity-started ICP as the
+ * fallback.  The network is the library's own (not in the paper):
+ *
+ *   input   x[n][32][256][2] bfloat16, NHWC: channel 0 keyframe, 1 scan,
+ *           1/range of pixel (y rows/32, x cols/256), 0 where there is no
+ *           valid return;
+ *   layers  five 3x3 convolutions with ReLU, width circular, height
+ *           zero-padded, (cin, cout, stride) = (2,32,2) (32,64,2) (64,96,2)
+ *           (96,128,2) (128,128,1), BF16 operands on the matrix cores with
+ *           FP32 accumulation, activations stored as bfloat16; then a fully
+ *           connected FP32 layer 4096 -> 6 over the NHWC flattening;
+ *   output  y[n][6]: the scan -> keyframe pose (Exp(0.25 y[0:3]), 1.0 y[3:6])
+ *           (rotation vector in rad, translation in m);
+ *   params  FP32, flattened per layer: conv W [9 cin][cout] (row
+ *           (3 ky + kx) cin + ci), conv b [cout], ..., FC W [6][4096], FC b [6];
+ *   loss    sum of squared output errors / (2 n); optimiser Adam with
+ *           beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
+ * ------------------------------------------------------------------------ */
+
+#define UPS_PROPOSAL_ROWS 32
+#define UPS_PROPOSAL_COLS 256
+
+typedef struct ups_proposal ups_proposal;
+
+/* A range image the network input is taken from: range of pixel (i, j) at
+ * range_d[(i * cols + j) * stride] (stride 1 for a depth image; a surfel
+ * image's range channel is surfel_d + 3 with stride 4).  rows and cols must be
+ * multiples of 32 and 256; a range is valid iff finite and r_min < r <= r_max. */
+typedef struct {
+    const float *range_d;
+    int32_t rows, cols, stride;
+    float r_min, r_max;
+} ups_range_image;
+
+/* Number of network parameters (357382). */
+int64_t ups_proposal_num_params(void);
+
+/* A proposal network for batches of up to max_batch pairs on the context's
+ * device: parameters (zero), Adam state, activations and workspace.  Synchronous;
+ * allocates device memory. */
+ups_status ups_proposal_create(ups_context *ctx, int32_t max_batch, ups_proposal **out);
+void ups_proposal_destroy(ups_proposal *p);
+
+/* Host <-> device parameter copies (synchronous).  set_params also resets the
+ * Adam moments and step count. */
+ups_status ups_proposal_set_params(ups_proposal *p, const float *params_h, int64_t n);
+ups_status ups_proposal_get_params(ups_proposal *p, float *params_h, int64_t n);
+/* Gradient of the last training step. */
+ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n);
+
+/* Record the n (keyframe, scan) image pairs ups_proposal_input reads
+ * (synchronous upload of n descriptors; the images must stay alive). */
+ups_status ups_proposal_plan_input(ups_proposal *p, int32_t n, const ups_range_image *kf_h,
+                                   const ups_range_image *scan_h);
+
+/* Network input of the planned pairs into x_d[n][32][256][2] (bfloat16 bits),
+ * or into the proposal's own input buffer when x_d is NULL. */
+ups_status ups_proposal_input(ups_proposal *p, uint16_t *x_d, void *stream);
+
+/* y_d[n][6] from x_d (NULL: the proposal's own input buffer). */
+ups_status ups_proposal_forward(ups_proposal *p, int32_t n, const uint16_t *x_d, float *y_d, void *stream);
+
+/* poses_d[n] (FP64, scan -> keyframe) from network outputs y_d[n][6]. */
+ups_status ups_proposal_poses(ups_proposal *p, int32_t n, const float *y_d, ups_pose *poses_d, void *stream);
+
+/* One Adam step on the batch (x_d, target_d[n][6]) with learning rate lr:
+ * forward, loss, backward, update.  loss_d (device float, may be NULL)
+ * receives the batch loss before the update. */
+ups_status ups_proposal_train_step(ups_proposal *p, int32_t n, const uint16_t *x_d, const float *target_d, float lr,
+                                   float *loss_d, void *stream);
+
+/* The network's convolution as separate passes, for any shape (cout a
+ * multiple of 4, stride 1 or 2, width a multiple of the stride).  NHWC
+ * tensors; x, y bfloat16 bits; dy, dx, dw, db FP32.
+ *   forward:          y = relu(conv(x, W) + b), W given as w_nk[cout][9 cin]
+ *                     (the transpose of the [9 cin][cout] layout), bfloat16;
+ *   backward (data):  dx = dL/dx from y and dy = dL/dy, W as w_kn[9 cin][cout];
+ *   backward (wgt):   dw[9 cin][cout] and db[cout] from x, y, dy, with a
+ *                     workspace of ups_conv3x3_backward_weight_work() floats. */
+ups_status ups_conv3x3_forward(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t stride,
+                               const uint16_t *x_d, const uint16_t *w_nk_d, const float *b_d, uint16_t *y_d,
+                               void *stream);
+ups_status ups_conv3x3_backward_data(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t stride,
+                                     const uint16_t *y_d, const float *dy_d, const uint16_t *w_kn_d, float *dx_d,
+                                     void *stream);
+int64_t ups_conv3x3_backward_weight_work(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t stride);
+ups_status ups_conv3x3_backward_weight(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout, int32_t stride,
+                                       const uint16_t *x_d, const uint16_t *y_d, const float *dy_d, float *dw_d,
+                                       float *db_d, float *work_d, int64_t work_floats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,10 +115,31 @@ def load():
         "ups_autotune": [_P, ctypes.c_char_p],
         "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
     }
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    sig.update({
+        "ups_proposal_create": [_P, i32, ctypes.POINTER(_P)],
+        "ups_proposal_set_params": [_P, _P, i64],
+        "ups_proposal_get_params": [_P, _P, i64],
+        "ups_proposal_get_grads": [_P, _P, i64],
+        "ups_proposal_plan_input": [_P, i32, _P, _P],
+        "ups_proposal_input": [_P, _P, _P],
+        "ups_proposal_forward": [_P, i32, _P, _P, _P],
+        "ups_proposal_poses": [_P, i32, _P, _P, _P],
+        "ups_proposal_train_step": [_P, i32, _P, _P, f32, _P, _P],
+        "ups_conv3x3_forward": [i32, i32, i32, i32, i32, i32, _P, _P, _P, _P, _P],
+        "ups_conv3x3_backward_data": [i32, i32, i32, i32, i32, i32, _P, _P, _P, _P, _P],
+        "ups_conv3x3_backward_weight": [i32, i32, i32, i32, i32, i32, _P, _P, _P, _P, _P, _P, i64, _P],
+    })
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    lib.ups_proposal_num_params.argtypes = []
+    lib.ups_proposal_num_params.restype = ctypes.c_int64
+    lib.ups_conv3x3_backward_weight_work.argtypes = [ctypes.c_int32] * 6
+    lib.ups_conv3x3_backward_weight_work.restype = ctypes.c_int64
+    lib.ups_proposal_destroy.argtypes = [_P]
+    lib.ups_proposal_destroy.restype = None
     lib.ups_batch_destroy.argtypes = [_P]
     lib.ups_batch_destroy.restype = None
     lib.ups_context_destroy.argtypes = [_P]
@@ -503,3 +524,161 @@ def read_result_bytes(raw: bytes) -> dict:
                 valid=r.valid, iters_run=r.iters_run, status=r.status, level_iters=list(r.level_iters),
                 JtJ=np.array(r.JtJ[:]),
                 Jtr=np.array(r.Jtr[:]), last_update_norm=r.last_update_norm)
+
+
+# ---------------------------------------------------------------------------
+# learned pose proposal
+# ---------------------------------------------------------------------------
+
+PROPOSAL_ROWS, PROPOSAL_COLS = 32, 256
+
+
+class ups_range_image(ctypes.Structure):
+    _fields_ = [("range_d", _P), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("r_min", ctypes.c_float), ("r_max", ctypes.c_float)]
+
+
+def range_image(t, geom=None):
+    """Descriptor of a device range source: a float32 depth image [rows, cols]
+    or the range channel of a surfel image [rows, cols, 4]."""
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise UpsError("range source must be a contiguous CUDA float32 tensor")
+    if t.dim() == 3 and t.shape[2] == 4:
+        ptr, stride = t.data_ptr() + 12, 4
+    elif t.dim() == 2:
+        ptr, stride = t.data_ptr(), 1
+    else:
+        raise UpsError("range source must be [rows, cols] or [rows, cols, 4]")
+    r_min = float(geom.r_min) if geom is not None else 0.0
+    r_max = float(geom.r_max) if geom is not None else 50.0
+    return ups_range_image(_P(ptr), int(t.shape[0]), int(t.shape[1]), stride, r_min, r_max)
+
+
+def proposal_num_params() -> int:
+    return int(load().ups_proposal_num_params())
+
+
+class Proposal:
+    """The pose-proposal network on the GPU (parameters, Adam state and
+    buffers for batches of up to ``max_batch`` pairs)."""
+
+    def __init__(self, ctx: Context, max_batch: int):
+        h = _P()
+        _check(load().ups_proposal_create(ctx.handle, int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self.max_batch = max_batch
+        self.n_params = proposal_num_params()
+        self._planned = None
+
+    def set_params(self, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        if a.size != self.n_params:
+            raise UpsError("parameter count mismatch")
+        _check(_LIB.ups_proposal_set_params(self._h, a.ctypes.data_as(_P), int(a.size)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(_LIB.ups_proposal_get_params(self._h, a.ctypes.data_as(_P), int(a.size)))
+        return a
+
+    def get_grads(self) -> np.ndarray:
+        a = np.empty(self.n_params, dtype=np.float32)
+        _check(_LIB.ups_proposal_get_grads(self._h, a.ctypes.data_as(_P), int(a.size)))
+        return a
+
+    def plan_input(self, kf_sources, scan_sources, kf_geoms=None, scan_geoms=None):
+        """Record (keyframe, scan) range sources (tensors, see range_image)."""
+        n = len(kf_sources)
+        kf = (ups_range_image * n)(*[range_image(t, kf_geoms[k] if kf_geoms else None)
+                                     for k, t in enumerate(kf_sources)])
+        sc = (ups_range_image * n)(*[range_image(t, scan_geoms[k] if scan_geoms else None)
+                                     for k, t in enumerate(scan_sources)])
+        _check(_LIB.ups_proposal_plan_input(self._h, n, ctypes.cast(kf, _P), ctypes.cast(sc, _P)))
+        self._planned = (n, list(kf_sources), list(scan_sources))
+
+    def input(self, x=None):
+        """Network input of the planned pairs into ``x`` (bfloat16 [n, 32, 256, 2])
+        or, when None, into the proposal's own buffer."""
+        torch = _torch()
+        ptr = None if x is None else _dev_ptr(x, torch.bfloat16, "input")
+        _check(_LIB.ups_proposal_input(self._h, ptr, _stream()))
+        return x
+
+    def forward(self, n: int, x=None, y=None):
+        torch = _torch()
+        if y is None:
+            y = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        ptr = None if x is None else _dev_ptr(x, torch.bfloat16, "input")
+        _check(_LIB.ups_proposal_forward(self._h, int(n), ptr, _dev_ptr(y, torch.float32, "output"), _stream()))
+        return y
+
+    def poses(self, y, poses=None):
+        torch = _torch()
+        n = y.shape[0]
+        if poses is None:
+            poses = torch.empty((n, 12), dtype=torch.float64, device=y.device)
+        _check(_LIB.ups_proposal_poses(self._h, int(n), _dev_ptr(y, torch.float32, "output"),
+                                       _dev_ptr(poses, torch.float64, "poses"), _stream()))
+        return poses
+
+    def train_step(self, x, target, lr: float, loss=None):
+        torch = _torch()
+        n = target.shape[0]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        xp = None if x is None else _dev_ptr(x, torch.bfloat16, "input")
+        _check(_LIB.ups_proposal_train_step(self._h, int(n), xp, _dev_ptr(target, torch.float32, "target"),
+                                            float(lr), _dev_ptr(loss, torch.float32, "loss"), _stream()))
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.ups_proposal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def conv3x3_forward(x, w_nk, b, cout, stride):
+    """y = relu(conv(x) + b); x bfloat16 [n, h, w, cin], w_nk bfloat16 [cout, 9 cin]."""
+    torch = _torch()
+    n, h, w, cin = x.shape
+    ho, wo = (h - 1) // stride + 1, (w - 1) // stride + 1
+    y = torch.empty((n, ho, wo, cout), dtype=torch.bfloat16, device=x.device)
+    _check(load().ups_conv3x3_forward(n, h, w, cin, cout, stride, _dev_ptr(x, torch.bfloat16, "x"),
+                                      _dev_ptr(w_nk, torch.bfloat16, "w"), _dev_ptr(b, torch.float32, "b"),
+                                      _dev_ptr(y, torch.bfloat16, "y"), _stream()))
+    return y
+
+
+def conv3x3_backward_data(y, dy, w_kn, h, w, cin, stride):
+    torch = _torch()
+    n, _, _, cout = y.shape
+    dx = torch.empty((n, h, w, cin), dtype=torch.float32, device=y.device)
+    _check(load().ups_conv3x3_backward_data(n, h, w, cin, cout, stride, _dev_ptr(y, torch.bfloat16, "y"),
+                                            _dev_ptr(dy, torch.float32, "dy"), _dev_ptr(w_kn, torch.bfloat16, "w"),
+                                            _dev_ptr(dx, torch.float32, "dx"), _stream()))
+    return dx
+
+
+def conv3x3_backward_weight(x, y, dy, stride):
+    torch = _torch()
+    n, h, w, cin = x.shape
+    cout = y.shape[3]
+    lib = load()
+    wf = int(lib.ups_conv3x3_backward_weight_work(n, h, w, cin, cout, stride))
+    if wf < 0:
+        raise UpsError("invalid convolution shape")
+    work = torch.empty(max(wf, 1), dtype=torch.float32, device=x.device)
+    dw = torch.empty((9 * cin, cout), dtype=torch.float32, device=x.device)
+    db = torch.empty(cout, dtype=torch.float32, device=x.device)
+    _check(lib.ups_conv3x3_backward_weight(n, h, w, cin, cout, stride, _dev_ptr(x, torch.bfloat16, "x"),
+                                           _dev_ptr(y, torch.bfloat16, "y"), _dev_ptr(dy, torch.float32, "dy"),
+                                           _dev_ptr(dw, torch.float32, "dw"), _dev_ptr(db, torch.float32, "db"),
+                                           _dev_ptr(work, torch.float32, "work"), wf, _stream()))
+    return dw, db
