@@ -15,7 +15,11 @@ Second workload (batched): 256 independent registrations of panorama pairs
 of sizes drawn from {64x512, 64x1024, 128x1024, 128x2048} (box room or
 outdoor scene, motions up to 10 deg / 1 m), identity start, 3 levels of at
 most 10 iterations with an early exit below a 1e-6 update norm.  One step =
-normals of all 512 panoramas + all 256 registrations, replayed from a graph.
+surfels of the 256 scans + all 256 registrations against resident keyframe
+surfel images, replayed from a graph.  The same batch is then run started
+from the learned proposal network (input, network, poses, registration and
+the identity-started fallback in one graph), and both starts are compared on
+256 held-out pairs with motions up to 30 deg / 2 m.
 
 The roofline objects cover the level-0 Gauss-Newton launch of each workload
 (timed with HIP events on its own stream); the cpu_baseline object times the
@@ -55,6 +59,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variants")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--precision", choices=["kahan", "f32", "f64"], default="kahan",
@@ -241,7 +246,7 @@ def run_batch(args, torch, ups, synth, W, stream):
     log(f"rendered {N_BATCH} pairs in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     tot_px = sum(p["geom"].rows * p["geom"].cols for p in pairs)
-    ctx = ups.Context(0, max_pixels=128 * 2048, max_batch=N_BATCH, max_batch_pixels=tot_px)
+    ctx = ups.Context(0, max_pixels=128 * 2048, max_batch=N_BATCH, max_batch_pixels=N_BATCH * 128 * 2048)
     tune = "measured"
     if os.path.exists(args.tune_cache):
         tune = "cache"
@@ -318,9 +323,124 @@ def run_batch(args, torch, ups, synth, W, stream):
                      "kernel": f"k_icp_batch<{K[0]},{args.precision},iter> (level-0 launch over all {N_BATCH})",
                      "launch_us": round(launch_us, 2), "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if not args.no_proposal:
+        out["learned"] = run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms, res)
     batch.close()
     ctx.close()
     return out
+
+
+def _successes(res, pairs, synth):
+    ok = []
+    for r, p in zip(res, pairs):
+        rot, tr = synth.pose_error(r["T"], p["T_gt"])
+        ok.append(rot < np.radians(1.0) and tr < 0.05)
+    return np.array(ok)
+
+
+def _errors(res, pairs, synth):
+    e = np.array([synth.pose_error(r["T"], p["T_gt"]) for r, p in zip(res, pairs)])
+    return {"median_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
+            "p95_rad_m": [float(np.percentile(e[:, 0], 95)), float(np.percentile(e[:, 1], 95))]}
+
+
+def run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms_plain, res_plain):
+    """The same batch started from the network's proposals, with the
+    identity-started fallback: one step = scan surfels + network input +
+    network + poses + registration + fallback, replayed from a graph."""
+    from paper_2101_00585_amd import proposal as P
+    n = len(items)
+    prop = ups.Proposal(ctx, n)
+    prop.set_params(P.load_params())
+    pr = P.ProposedRegistration(ctx, prop, batch, items)
+    results = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+
+    def step():
+        batch.normals()
+        pr.run(results)
+
+    step()
+    torch.cuda.synchronize()
+    res = ups.read_results(results)
+    ms = time_graph(torch, capture(torch, stream, step), stream, args.batch_steps)
+    ms_net = time_graph(torch, capture(torch, stream, lambda: (prop.input(), prop.forward(n, None, pr.y))), stream,
+                        args.batch_steps)
+    tot_px = sum(p["geom"].rows * p["geom"].cols for p in pairs)
+    px_it = sum(sum(r["level_iters"][l] * (p["geom"].rows >> l) * (p["geom"].cols >> l) for l in range(LEVELS))
+                for r, p in zip(res, pairs))
+    eq128 = tot_px / (128 * 1024)
+    log(f"batched+learned: {ms:.3f} ms per {n} registrations ({ms_plain:.3f} ms from the identity), "
+        f"network {ms_net:.3f} ms, {sum(r['status'] == 4 for r in res)} fallbacks")
+    wide = {name: run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed)
+            for name, max_deg, seed in (("30deg_2m", 30.0, 4_000_000), ("90deg_2m", 90.0, 4_100_000))}
+    prop.close()
+    return {
+        "workload": "the batch above started from the proposal network's poses (BF16 MFMA CNN on 32x256 "
+                    "inverse-range pairs), identity-started fallback below inlier ratio 0.5",
+        "ms_per_batch": round(ms, 4),
+        "registrations_per_s": round(n / ms * 1e3, 1),
+        "ms_per_128x1024_equivalent": round(ms / eq128, 5),
+        "ms_network_input_and_forward": round(ms_net, 4),
+        "pixel_iterations_executed": int(px_it),
+        "fallbacks_used": int(sum(r["status"] == 4 for r in res)),
+        "success_within_1deg_5cm": [int(_successes(res, pairs, synth).sum()),
+                                    int(_successes(res_plain, pairs, synth).sum()), n],
+        "pose_error_vs_truth": _errors(res, pairs, synth),
+        "wide_motion": wide,
+    }
+
+
+def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
+    """Motions up to max_deg / 2 m (held-out seeds): identity start against
+    proposal start + fallback, success rates, pixel-iterations and times."""
+    from paper_2101_00585_amd import proposal as P
+    from synth import workloads as W
+    pairs = [W.batch_pair(k, base_seed=seed, max_angle=np.radians(max_deg), max_trans=2.0) for k in range(n)]
+    dev = torch.device("cuda")
+    items = []
+    for p in pairs:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g, scan_depth=torch.from_numpy(p["scan"]).to(dev),
+                          kf_surfel=ups.panorama_normals(ctx, g, torch.from_numpy(p["kf"]).to(dev)),
+                          scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev)))
+    torch.cuda.synchronize()
+    batch = ups.Batch(ctx, items, ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6))
+    init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
+    r_plain = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
+    r_prop = torch.zeros_like(r_plain)
+    pr = P.ProposedRegistration(ctx, prop, batch, items)
+
+    def plain():
+        batch.normals()
+        batch.register(init, r_plain)
+
+    def learned():
+        batch.normals()
+        pr.run(r_prop)
+
+    plain()
+    learned()
+    torch.cuda.synchronize()
+    res_p, res_l = ups.read_results(r_plain), ups.read_results(r_prop)
+    ms_p = time_graph(torch, capture(torch, stream, plain), stream, args.batch_steps)
+    ms_l = time_graph(torch, capture(torch, stream, learned), stream, args.batch_steps)
+    s_p, s_l = _successes(res_p, pairs, synth), _successes(res_l, pairs, synth)
+
+    def px_it(res):
+        return int(sum(sum(r["level_iters"][l] * (p["geom"].rows >> l) * (p["geom"].cols >> l) for l in range(LEVELS))
+                       for r, p in zip(res, pairs)))
+
+    log(f"motions up to {max_deg:.0f} deg / 2 m: success identity {s_p.sum()}/{n} in {ms_p:.3f} ms, "
+        f"proposal {s_l.sum()}/{n} in {ms_l:.3f} ms")
+    batch.close()
+    return {"workload": f"{n} held-out pairs, batch sizes and scenes, motions up to {max_deg:.0f} deg / 2 m",
+            "pixel_iterations_identity_start": px_it(res_p), "pixel_iterations_proposal_start": px_it(res_l),
+            "success_within_1deg_5cm_identity_start": int(s_p.sum()),
+            "success_within_1deg_5cm_proposal_start": int(s_l.sum()),
+            "ms_per_batch_identity_start": round(ms_p, 4), "ms_per_batch_proposal_start": round(ms_l, 4),
+            "fallbacks_used": int(sum(r["status"] == 4 for r in res_l)), "n": n,
+            "pose_error_vs_truth_identity_start": _errors(res_p, pairs, synth),
+            "pose_error_vs_truth_proposal_start": _errors(res_l, pairs, synth)}
 
 
 def main():
@@ -370,6 +490,9 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = run_batch(args, torch, ups, synth, W, stream)
+        out["config"]["ms_per_128x1024_batched"] = out["batched"]["ms_per_128x1024_equivalent"]
+        if "learned" in out["batched"]:
+            out["config"]["ms_per_128x1024_batched_learned"] = out["batched"]["learned"]["ms_per_128x1024_equivalent"]
     if not args.no_cpu_baseline:
         model, ncpu = cpu_info()
         log(f"cpu baseline (oracle, 1 thread) on {model}")

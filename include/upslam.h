@@ -280,6 +280,16 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
 ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d,
                               void *stream);
 
+/* Fallback of proposal-started registrations (the learned proposal below):
+ * call right after ups_register_batch on the same batch with its results.
+ * Registrations whose inlier ratio is below min_inlier_ratio are registered
+ * again from the identity (with the pyramids of that call); where the second
+ * run ends with a lower truncated cost its result replaces the first in
+ * results_d, with status UPS_FALLBACK_USED.  The others are not run again.
+ * Enqueues only kernels (graph-capturable). */
+ups_status ups_register_batch_fallback(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
+                                       ups_icp_result *results_d, void *stream);
+
 /* Autotune the pixels per thread of batch launches for this device: times the
  * Gauss-Newton launch at 1, 2, 4, ..., 64 pixels per thread on synthetic
  * batches of each lidar panorama size (16x128 ... 128x2048) and keeps the

@@ -26,6 +26,7 @@ _SO = os.path.join(_HERE, "libupslam.so")
 _LIB = None
 
 STATUS = {0: "CONVERGED", 1: "MAX_ITERS", 2: "DEGENERATE", 3: "NO_INLIERS", 4: "FALLBACK_USED"}
+STATUS_CONVERGED, STATUS_MAX_ITERS, STATUS_DEGENERATE, STATUS_NO_INLIERS, STATUS_FALLBACK_USED = range(5)
 PREC_KAHAN_F64 = 0
 PREC_F32 = 1
 PREC_F64 = 2
@@ -111,6 +112,7 @@ def load():
         "ups_batch_create": [_P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)],
         "ups_batch_normals": [_P, _P, _P, _P],
         "ups_register_batch": [_P, _P, _P, _P, _P],
+        "ups_register_batch_fallback": [_P, _P, ctypes.c_double, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
         "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
@@ -467,6 +469,15 @@ class Batch:
         _check(_LIB.ups_batch_create(ctx.handle, self.n, ctypes.cast(arr, _P), ctypes.byref(pc),
                                      int(pixels_per_thread), ctypes.byref(h)))
         self._h = h
+
+    def fallback(self, results, min_inlier_ratio: float):
+        """Rerun from the identity the registrations whose ``results`` (from
+        ``register``) have an inlier ratio below ``min_inlier_ratio``; keep
+        the better of the two by truncated cost (status FALLBACK_USED)."""
+        torch = _torch()
+        _check(_LIB.ups_register_batch_fallback(self.ctx.handle, self._h, float(min_inlier_ratio),
+                                                _dev_ptr(results, torch.uint8, "results"), _stream()))
+        return results
 
     def pixels_per_thread(self):
         out = (ctypes.c_int32 * 4)()

@@ -9,6 +9,7 @@
 // launch and one finish launch (a block per registration).  Registrations
 // whose level converged or that failed leave their tiles idle.
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,10 @@ struct ups_batch {
     int *d_ntile_start = nullptr;
     float4 *ntmp = nullptr;
     int n_nimg = 0, total_ntiles = 0;
+    // identity-started fallback
+    ups_pose *ident = nullptr;       // [n] identity poses
+    uint8_t *mask = nullptr;         // [n] registrations the fallback reruns
+    ups_icp_result *alt = nullptr;   // [n] fallback results
 };
 
 namespace {
@@ -61,6 +66,9 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->d_nimg);
     (void)hipFree(b->d_ntile_start);
     (void)hipFree(b->ntmp);
+    (void)hipFree(b->ident);
+    (void)hipFree(b->mask);
+    (void)hipFree(b->alt);
     delete b;
 }
 
@@ -188,6 +196,17 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->pyr, std::max<int64_t>(pyr_total, 1) * sizeof(float4));
     alloc((void **)&b->state, (size_t)n * 2 * sizeof(RegState));
     alloc((void **)&b->partials, (size_t)n * 2 * pstride * kPartialStride * sizeof(double));
+    alloc((void **)&b->ident, (size_t)n * sizeof(ups_pose));
+    alloc((void **)&b->mask, (size_t)n);
+    alloc((void **)&b->alt, (size_t)n * sizeof(ups_icp_result));
+    if (e == hipSuccess) {
+        std::vector<ups_pose> id(n);
+        for (ups_pose &q : id) {
+            memset(&q, 0, sizeof(q));
+            q.R[0] = q.R[4] = q.R[8] = 1.0;
+        }
+        e = hipMemcpy(b->ident, id.data(), n * sizeof(ups_pose), hipMemcpyHostToDevice);
+    }
     if (!nimg.empty()) {
         alloc((void **)&b->d_nimg, nimg.size() * sizeof(NormImg));
         alloc((void **)&b->ntmp, ntmp_total * sizeof(float4));
@@ -305,18 +324,18 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
     return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p, (hipStream_t)stream);
 }
 
-ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d,
-                              void *stream) {
-    UPS_REQUIRE(ctx && b, "null argument");
+}  // extern "C"
+
+namespace {
+
+// The launch sequence of a batch call; with a mask only the masked-in
+// registrations run (their pyramids left by the previous call are reused).
+ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
+                               hipStream_t s) {
     ups_status st;
-    if ((st = check_ptr(init_d, 8, "init poses")) != UPS_OK) return st;
-    if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
-    Guard dg(ctx->device);
-    UPS_CHECK_HIP(dg.err);
-    hipStream_t s = (hipStream_t)stream;
     const ups_icp_params &p = b->p;
     const int n = b->n;
-    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, s)) != UPS_OK)
+    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, mask, s)) != UPS_OK)
         return st;
     StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -348,6 +367,35 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
                                s)) != UPS_OK)
         return st;
     return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d,
+                              void *stream) {
+    UPS_REQUIRE(ctx && b, "null argument");
+    ups_status st;
+    if ((st = check_ptr(init_d, 8, "init poses")) != UPS_OK) return st;
+    if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    return register_batch_impl(b, init_d, nullptr, results_d, (hipStream_t)stream);
+}
+
+ups_status ups_register_batch_fallback(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
+                                       ups_icp_result *results_d, void *stream) {
+    UPS_REQUIRE(ctx && b, "null argument");
+    UPS_REQUIRE(std::isfinite(min_inlier_ratio), "min_inlier_ratio must be finite");
+    ups_status st;
+    if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = launch_fallback_mask(b->n, results_d, min_inlier_ratio, b->mask, s)) != UPS_OK) return st;
+    if ((st = register_batch_impl(b, b->ident, b->mask, b->alt, s)) != UPS_OK) return st;
+    return launch_fallback_merge(b->n, results_d, b->alt, b->mask, s);
 }
 
 }  // extern "C"

@@ -45,6 +45,17 @@ __device__ __forceinline__ float2 ldg(const float2 *p, int idx) {
     return make_float2(v.x, v.y);
 }
 __device__ __forceinline__ float ldg(const float *p, int idx) { return ((const UPS_AS_GLOBAL float *)p)[idx]; }
+// The same with a non-negative index whose byte offset fits in 32 bits: the
+// load takes the (wave-uniform) base in scalar registers and a 32-bit vector
+// offset, with no 64-bit address arithmetic per lane.
+__device__ __forceinline__ float4 ldg_u(const float4 *p, uint32_t idx) {
+    const v4f v = *(const UPS_AS_GLOBAL v4f *)((const UPS_AS_GLOBAL char *)p + (idx << 4));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ldg_u(const float2 *p, uint32_t idx) {
+    const v2f v = *(const UPS_AS_GLOBAL v2f *)((const UPS_AS_GLOBAL char *)p + (idx << 3));
+    return make_float2(v.x, v.y);
+}
 // idx must be the same in every lane of the wavefront
 __device__ __forceinline__ float2 lds_uniform(const float2 *p, int idx) {
     const v2f v = ((const UPS_AS_CONST v2f *)p)[idx];
@@ -182,9 +193,9 @@ __device__ __forceinline__ Gather scan_side(const DGeom &sg, float4 s2, float2 e
     int ki, kj;
     if (!project(kg, G.q, ki, kj)) return G;
     G.kf_index = ki * kg.cols + kj;
-    G.s1 = ldg(kf, G.kf_index);
-    G.e = ldg(kg.lut_row, ki * kg.stride);
-    G.a = ldg(kg.lut_col, kj * kg.stride);
+    G.s1 = ldg_u(kf, (uint32_t)G.kf_index);
+    G.e = ldg_u(kg.lut_row, (uint32_t)(ki * kg.stride));
+    G.a = ldg_u(kg.lut_col, (uint32_t)(kj * kg.stride));
     return G;
 }
 

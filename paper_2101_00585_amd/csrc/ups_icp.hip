@@ -345,10 +345,11 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     // column of this thread's pixel; it advances by kBlock mod cols per pixel
     const int col_step = kBlock % sg.cols;
     int jn = (base + tid) % sg.cols;
-    float4 nxt = ldg(scan, min(base + tid, npix - 1));
-    float2 nxt_a = ldg(sg.lut_col, jn * sg.stride);
+    float4 nxt = ldg_u(scan, (uint32_t)min(base + tid, npix - 1));
+    float2 nxt_a = ldg_u(sg.lut_col, (uint32_t)(jn * sg.stride));
     if (!FUSED) {
         if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
+        if (MODE == MODE_EVAL && slot_in->skip) return;
         if (tid == 0) S = *slot_in;
         __syncthreads();
     } else {
@@ -407,8 +408,8 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
             const int pn = base + (k + 1) * kBlock + tid;
             jn += col_step;
             jn = jn >= sg.cols ? jn - sg.cols : jn;
-            nxt = ldg(scan, min(pn, npix - 1));
-            nxt_a = ldg(sg.lut_col, jn * sg.stride);
+            nxt = ldg_u(scan, (uint32_t)min(pn, npix - 1));
+            nxt_a = ldg_u(sg.lut_col, (uint32_t)(jn * sg.stride));
         }
         bool inl;
         float r;
@@ -501,6 +502,7 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_
     __shared__ Acc rows[31][16];
     __shared__ Acc tot[32];
     const RegState *S = I.state + parity;
+    if (S->skip) return;  // masked out of this batch call: the result is left as it was
     reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, npartials_of(I.nblocks[0]),
                              rows, tot);
     if (threadIdx.x != 0) return;
@@ -615,9 +617,11 @@ __global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *
 // other blocks build the pyramids, one thread per level-1 pixel, found
 // through the prefix table of per-registration level-1 pixel counts (scan,
 // then keyframe).
+// With a mask, registrations whose mask byte is 0 are marked to skip the call.
 __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict__ insts, const ups_pose *init,
                                                           int n, int levels, int init_blocks,
-                                                          const int *__restrict__ pix_start) {
+                                                          const int *__restrict__ pix_start,
+                                                          const uint8_t *__restrict__ mask) {
     if ((int)blockIdx.x < init_blocks) {
         const int k = blockIdx.x * kBlock + threadIdx.x;
         if (k >= n) return;
@@ -628,6 +632,11 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict
         S.status = UPS_CONVERGED;
         S.level_active = 1;
         S.active = 1;
+        if (mask && !mask[k]) {
+            S.skip = 1;
+            S.stop = 1;
+            S.active = 0;
+        }
         insts[k].state[0] = S;
         return;
     }
@@ -646,11 +655,45 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict
     else pyramid_from_level1(I.kg, I.kf, levels, q - n0);
 }
 
+// mask: null = every registration, pyramids built; else only the masked-in
+// registrations run and the pyramids of the previous call are reused.
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
-                                int total_pix, hipStream_t s) {
+                                int total_pix, const uint8_t *mask, hipStream_t s) {
     const int ib = (n + kBlock - 1) / kBlock;
-    const int pb = (total_pix + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_prepare_batch, dim3(ib + pb), dim3(kBlock), 0, s, insts, init, n, levels, ib, pix_start);
+    const int pb = mask ? 0 : (total_pix + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_prepare_batch, dim3(ib + pb), dim3(kBlock), 0, s, insts, init, n, levels, ib, pix_start,
+                       mask);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+__global__ void k_fallback_mask(int n, const ups_icp_result *__restrict__ res, double min_ratio,
+                                uint8_t *__restrict__ mask) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) mask[k] = res[k].inlier_ratio < min_ratio ? 1 : 0;
+}
+
+// Where the fallback ran and ended with a lower truncated cost, its result
+// replaces the first one, marked UPS_FALLBACK_USED.
+__global__ void k_fallback_merge(int n, ups_icp_result *__restrict__ res, const ups_icp_result *__restrict__ alt,
+                                 const uint8_t *__restrict__ mask) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n || !mask[k]) return;
+    if (alt[k].trunc_cost < res[k].trunc_cost) {
+        res[k] = alt[k];
+        res[k].status = UPS_FALLBACK_USED;
+    }
+}
+
+ups_status launch_fallback_mask(int n, const ups_icp_result *res, double min_ratio, uint8_t *mask, hipStream_t s) {
+    hipLaunchKernelGGL(k_fallback_mask, dim3((n + 255) / 256), dim3(256), 0, s, n, res, min_ratio, mask);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+ups_status launch_fallback_merge(int n, ups_icp_result *res, const ups_icp_result *alt, const uint8_t *mask,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_fallback_merge, dim3((n + 255) / 256), dim3(256), 0, s, n, res, alt, mask);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

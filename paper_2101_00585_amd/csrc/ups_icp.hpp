@@ -19,6 +19,7 @@ struct RegState {
     int npartials;      // number of those partials
     int level_iters[4]; // updates applied per level
     int active;         // batches: the next Gauss-Newton launch processes this registration
+    int skip;           // batches: the registration takes no part in this call (masked out)
 };
 
 // One registration as the kernels see it.
@@ -60,7 +61,10 @@ ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
                                hipStream_t s);
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
-                                int total_pix, hipStream_t s);
+                                int total_pix, const uint8_t *mask, hipStream_t s);
+ups_status launch_fallback_mask(int n, const ups_icp_result *res, double min_ratio, uint8_t *mask, hipStream_t s);
+ups_status launch_fallback_merge(int n, ups_icp_result *res, const ups_icp_result *alt, const uint8_t *mask,
+                                 hipStream_t s);
 __device__ __host__ inline int npartials_host(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
 
 }  // namespace ups

@@ -184,6 +184,37 @@ def test_batch_failures_isolated(gpu_lib, bctx, pairs):
     b.close()
 
 
+def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs):
+    """Registrations started 60 deg away end with a low inlier ratio and are
+    rerun from the identity; the fallback's result replaces theirs (status
+    FALLBACK_USED) and matches a plain identity-started registration, while
+    the others keep their results bit for bit."""
+    import torch
+    items = _items_from_depth(gpu_lib, pairs[:4])
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    plain = _np(b.register([np.eye(4)] * 4)).copy()
+    bad = synth.se3(synth.rot_z(np.radians(60.0)), [1.5, -1.0, 0.0])
+    init = [bad, np.eye(4), bad, np.eye(4)]
+    res = b.register(init)
+    torch.cuda.synchronize()
+    first = gpu_lib.read_results(res)
+    before = _np(res).copy()
+    b.fallback(res, 0.5)
+    torch.cuda.synchronize()
+    after = gpu_lib.read_results(res)
+    ref = gpu_lib.read_results(torch.from_numpy(plain))
+    for k in (0, 2):
+        assert first[k]["inlier_ratio"] < 0.5
+        assert after[k]["status"] == gpu_lib.STATUS_FALLBACK_USED
+        assert np.array_equal(after[k]["T"], ref[k]["T"])
+        assert after[k]["trunc_cost"] == ref[k]["trunc_cost"]
+    for k in (1, 3):
+        assert first[k]["inlier_ratio"] >= 0.5
+        assert np.array_equal(_np(res)[k], before[k])
+    b.close()
+
+
 def test_autotune_roundtrip(gpu_lib, bctx, tmp_path):
     path = str(tmp_path / "tune.json")
     gpu_lib.autotune(bctx, path)

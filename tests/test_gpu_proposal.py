@@ -1,0 +1,145 @@
+"""What the trained proposal network gains over identity-started ICP.
+
+Held-out pairs (seeds never used in training) of the batch workload's sizes
+and scenes, with motions up to 30 deg / 2 m (the training range) and with
+relative yaw up to 90 deg (loop-closure candidates).  Both arms run the same
+batched registration (3 levels, <= 10/10/10 iterations, early exit 1e-6);
+the proposal arm starts each registration from the network's pose and falls
+back to the identity start where the inlier ratio stays below 0.5.  A
+registration succeeds when it ends within 1 deg and 5 cm of the true motion.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N_PAIRS = 64
+RHO_MIN = 0.5
+SETS = {"30deg_2m": (30.0, 2.0, 2_000_000), "90deg_2m": (90.0, 2.0, 2_100_000)}
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _success(res, pairs):
+    out = []
+    for r, p in zip(res, pairs):
+        rot, tr = synth.pose_error(r["T"], p["T_gt"])
+        out.append(rot < math.radians(1.0) and tr < 0.05)
+    return np.array(out)
+
+
+def _pixel_iterations(res, pairs):
+    return sum(sum(r["level_iters"][l] * (p["geom"].rows >> l) * (p["geom"].cols >> l) for l in range(3))
+               for r, p in zip(res, pairs))
+
+
+@pytest.fixture(scope="module")
+def lib(gpu_lib):
+    from paper_2101_00585_amd import proposal as P
+    ctx = gpu_lib.Context(0, max_pixels=128 * 2048, max_batch=N_PAIRS, max_batch_pixels=N_PAIRS * 128 * 2048)
+    prop = gpu_lib.Proposal(ctx, N_PAIRS)
+    prop.set_params(P.load_params())
+    yield gpu_lib, ctx, prop
+    prop.close()
+    ctx.close()
+
+
+@pytest.fixture(scope="module", params=list(SETS))
+def arms(request, lib):
+    import torch
+    from paper_2101_00585_amd import proposal as P
+    ups, ctx, prop = lib
+    max_deg, max_t, seed = SETS[request.param]
+    pairs = [W.batch_pair(k, base_seed=seed, max_angle=math.radians(max_deg), max_trans=max_t)
+             for k in range(N_PAIRS)]
+    items = []
+    for p in pairs:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g, scan_depth=_t(p["scan"]), kf_depth=_t(p["kf"]),
+                          scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda"),
+                          kf_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda")))
+    b = ups.Batch(ctx, items, ups.IcpParams(**P.BATCH_ICP))
+    b.normals()
+    plain = ups.read_results(b.register([np.eye(4)] * N_PAIRS))
+    pr = P.ProposedRegistration(ctx, prop, b, items, RHO_MIN)
+    results = torch.zeros((N_PAIRS, ups.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    # the proposal start alone (no fallback), then the whole proposed path
+    prop.input()
+    prop.forward(N_PAIRS, None, pr.y)
+    prop.poses(pr.y, pr.poses)
+    started = ups.read_results(b.register(pr.poses))
+    proposed = ups.read_results(pr.run(results))
+    torch.cuda.synchronize()
+    out = dict(name=request.param, pairs=pairs, plain=plain, started=started, proposed=proposed, b=b, pr=pr,
+               results=results)
+    s_plain, s_start, s_prop = (_success(r, pairs) for r in (plain, started, proposed))
+    n_fb = sum(r["status"] == ups.STATUS_FALLBACK_USED for r in proposed)
+    # the rule the inlier-ratio proxy stands in for: fall back when the
+    # proposal-started registration's truncated cost exceeds the plain one by 5 %
+    rule = np.array([s["trunc_cost"] > 1.05 * p["trunc_cost"] for s, p in zip(started, plain)])
+    proxy = np.array([s["inlier_ratio"] < RHO_MIN for s in started])
+    print(f"\n{request.param}: success identity start {s_plain.sum()}/{N_PAIRS}, proposal start "
+          f"{s_start.sum()}/{N_PAIRS}, proposal + fallback {s_prop.sum()}/{N_PAIRS} ({n_fb} fallbacks used); "
+          f"pixel-iterations identity {_pixel_iterations(plain, pairs) / 1e6:.1f} M, proposal start "
+          f"{_pixel_iterations(started, pairs) / 1e6:.1f} M; proxy agrees with the 5 % rule on "
+          f"{(rule == proxy).sum()}/{N_PAIRS}")
+    yield out
+    b.close()
+
+
+def test_gain(arms):
+    """Up to 30 deg the identity start already converges (the coarse pyramid
+    level has a 2 m gate), and the proposal start reaches the same results
+    with no more Gauss-Newton work; at loop-closure yaw (up to 90 deg) the
+    proposal succeeds where the identity start does not."""
+    pairs = arms["pairs"]
+    s_plain, s_prop = _success(arms["plain"], pairs), _success(arms["proposed"], pairs)
+    if arms["name"] == "30deg_2m":
+        assert s_prop.sum() >= s_plain.sum() and s_prop.mean() >= 0.95
+        assert _pixel_iterations(arms["started"], pairs) <= _pixel_iterations(arms["plain"], pairs)
+    else:
+        assert s_prop.sum() >= s_plain.sum() + 0.1 * N_PAIRS
+        assert s_prop.mean() >= 0.8
+
+
+def test_equal_accuracy_where_both_succeed(arms):
+    """Where both starts succeed they reach the same optimum."""
+    pairs = arms["pairs"]
+    both = _success(arms["plain"], pairs) & _success(arms["proposed"], pairs)
+    assert both.sum() >= 0.3 * N_PAIRS
+    d = np.array([synth.pose_error(a["T"], b["T"]) for a, b, m in zip(arms["plain"], arms["proposed"], both) if m])
+    assert np.median(d[:, 0]) < 1e-4 and np.median(d[:, 1]) < 1e-3
+
+
+def test_fallback_only_where_flagged(arms, gpu_lib):
+    for s, r in zip(arms["started"], arms["proposed"]):
+        if s["inlier_ratio"] >= RHO_MIN:
+            assert r["status"] != gpu_lib.STATUS_FALLBACK_USED
+            assert np.array_equal(r["T"], s["T"])
+
+
+def test_proposed_path_replays_from_a_graph(arms):
+    import torch
+    pr, results = arms["pr"], arms["results"]
+    eager = results.cpu().numpy().copy()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        pr.run(results)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            pr.run(results)
+    for _ in range(2):
+        results.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(results.cpu().numpy(), eager)
