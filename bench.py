@@ -137,6 +137,23 @@ def time_graph(torch, graph, stream, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def time_checked(torch, g1, g2, count, stream, reps):
+    """Average ms of g1, a host read of count, and g2 when count > 0 (host
+    clock around synchronised steps)."""
+    with torch.cuda.stream(stream):
+        g1.replay()
+        if int(count.item()) > 0:
+            g2.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g1.replay()
+            if int(count.item()) > 0:
+                g2.replay()
+        torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
 def capture(torch, stream, fn):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.stream(stream):
@@ -357,12 +374,19 @@ def run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms_pl
 
     def step():
         batch.normals()
-        pr.run(results)
+        pr.propose_and_register(results)
 
-    step()
+    # one step: graph (scan surfels .. fallback plan), a host read of the
+    # fallback count, and the fallback launches only when it is not zero
+    g1 = capture(torch, stream, step)
+    g2 = capture(torch, stream, lambda: pr.batch.fallback_run(results))
+    ms = time_checked(torch, g1, g2, pr.count, stream, args.batch_steps)
+    with torch.cuda.stream(stream):
+        g1.replay()
+        if int(pr.count.item()) > 0:
+            g2.replay()
     torch.cuda.synchronize()
     res = ups.read_results(results)
-    ms = time_graph(torch, capture(torch, stream, step), stream, args.batch_steps)
     ms_net = time_graph(torch, capture(torch, stream, lambda: (prop.input(), prop.forward(n, None, pr.y))), stream,
                         args.batch_steps)
     tot_px = sum(p["geom"].rows * p["geom"].cols for p in pairs)
@@ -416,14 +440,21 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
 
     def learned():
         batch.normals()
-        pr.run(r_prop)
+        pr.propose_and_register(r_prop)
 
     plain()
-    learned()
     torch.cuda.synchronize()
-    res_p, res_l = ups.read_results(r_plain), ups.read_results(r_prop)
+    res_p = ups.read_results(r_plain)
     ms_p = time_graph(torch, capture(torch, stream, plain), stream, args.batch_steps)
-    ms_l = time_graph(torch, capture(torch, stream, learned), stream, args.batch_steps)
+    g1 = capture(torch, stream, learned)
+    g2 = capture(torch, stream, lambda: batch.fallback_run(r_prop))
+    ms_l = time_checked(torch, g1, g2, pr.count, stream, args.batch_steps)
+    with torch.cuda.stream(stream):
+        g1.replay()
+        if int(pr.count.item()) > 0:
+            g2.replay()
+    torch.cuda.synchronize()
+    res_l = ups.read_results(r_prop)
     s_p, s_l = _successes(res_p, pairs, synth), _successes(res_l, pairs, synth)
 
     def px_it(res):

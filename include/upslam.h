@@ -290,6 +290,15 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
 ups_status ups_register_batch_fallback(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
                                        ups_icp_result *results_d, void *stream);
 
+/* The two halves of ups_register_batch_fallback, for callers that skip the
+ * second when nothing needs it (its launch sequence has a fixed cost even
+ * when empty): plan flags the registrations to rerun and writes their number
+ * to count_d (device int32, may be NULL); run reruns the flagged ones of the
+ * last plan and merges their results into results_d. */
+ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
+                                   const ups_icp_result *results_d, int32_t *count_d, void *stream);
+ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result *results_d, void *stream);
+
 /* Autotune the pixels per thread of batch launches for this device: times the
  * Gauss-Newton launch at 1, 2, 4, ..., 64 pixels per thread on synthetic
  * batches of each lidar panorama size (16x128 ... 128x2048) and keeps the

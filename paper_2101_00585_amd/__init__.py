@@ -113,6 +113,8 @@ def load():
         "ups_batch_normals": [_P, _P, _P, _P],
         "ups_register_batch": [_P, _P, _P, _P, _P],
         "ups_register_batch_fallback": [_P, _P, ctypes.c_double, _P, _P],
+        "ups_batch_fallback_plan": [_P, _P, ctypes.c_double, _P, _P, _P],
+        "ups_batch_fallback_run": [_P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
         "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
@@ -477,6 +479,21 @@ class Batch:
         torch = _torch()
         _check(_LIB.ups_register_batch_fallback(self.ctx.handle, self._h, float(min_inlier_ratio),
                                                 _dev_ptr(results, torch.uint8, "results"), _stream()))
+        return results
+
+    def fallback_plan(self, results, min_inlier_ratio: float, count=None):
+        """First half of ``fallback``: flag the registrations to rerun; their
+        number goes to ``count`` (device int32 [1]) if given."""
+        torch = _torch()
+        cp = None if count is None else _dev_ptr(count, torch.int32, "count")
+        _check(_LIB.ups_batch_fallback_plan(self.ctx.handle, self._h, float(min_inlier_ratio),
+                                            _dev_ptr(results, torch.uint8, "results"), cp, _stream()))
+
+    def fallback_run(self, results):
+        """Second half of ``fallback``: rerun the flagged registrations and merge."""
+        torch = _torch()
+        _check(_LIB.ups_batch_fallback_run(self.ctx.handle, self._h, _dev_ptr(results, torch.uint8, "results"),
+                                           _stream()))
         return results
 
     def pixels_per_thread(self):

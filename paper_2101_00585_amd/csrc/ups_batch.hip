@@ -39,7 +39,14 @@ struct ups_batch {
     ups_pose *ident = nullptr;       // [n] identity poses
     uint8_t *mask = nullptr;         // [n] registrations the fallback reruns
     ups_icp_result *alt = nullptr;   // [n] fallback results
+    Compact *comp = nullptr;         // the registrations the fallback reruns ...
+    int *comp_list = nullptr;        // ... [n]
+    int *comp_start = nullptr;       // ... and their tile prefix tables [4][n+1]
 };
+
+// Grid of the launches over a subset of the batch (the fallback): they stride
+// over the subset's tiles, so that they cost little when it is small.
+constexpr int kListBlocks = 512, kListSolveBlocks = 32;
 
 namespace {
 
@@ -69,6 +76,7 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->ident);
     (void)hipFree(b->mask);
     (void)hipFree(b->alt);
+    (void)hipFree(b->comp);
     delete b;
 }
 
@@ -199,6 +207,11 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->ident, (size_t)n * sizeof(ups_pose));
     alloc((void **)&b->mask, (size_t)n);
     alloc((void **)&b->alt, (size_t)n * sizeof(ups_icp_result));
+    alloc((void **)&b->comp, sizeof(Compact) + ((size_t)n + 4 * ((size_t)n + 1)) * sizeof(int) + 64);
+    if (e == hipSuccess) {
+        b->comp_list = (int *)((char *)b->comp + 64);
+        b->comp_start = b->comp_list + n;
+    }
     if (e == hipSuccess) {
         std::vector<ups_pose> id(n);
         for (ups_pose &q : id) {
@@ -329,7 +342,8 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
 namespace {
 
 // The launch sequence of a batch call; with a mask only the masked-in
-// registrations run (their pyramids left by the previous call are reused).
+// registrations run (their pyramids left by the previous call are reused),
+// through the batch's Compact list of them.
 ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
                                hipStream_t s) {
     ups_status st;
@@ -351,21 +365,33 @@ ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8
         const int l = seq[q];
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
-        if ((st = launch_icp_batch(b->K[l], p.precision, MODE_ITER, b->d_inst, b->d_tile_start + l * (n + 1), n,
-                                   a, b->total_tiles[l], s)) != UPS_OK)
-            return st;
+        if (mask)
+            st = launch_icp_batch_list(b->K[l], p.precision, MODE_ITER, b->d_inst, b->comp, b->comp_list,
+                                       b->comp_start + l * (n + 1), n, a, std::min(b->total_tiles[l], kListBlocks), s);
+        else
+            st = launch_icp_batch(b->K[l], p.precision, MODE_ITER, b->d_inst, b->d_tile_start + l * (n + 1), n, a,
+                                  b->total_tiles[l], s);
+        if (st != UPS_OK) return st;
         StepArgs sa = a;
         sa.prev_level = l;
         sa.first_of_level = (q + 1 < seq.size() && seq[q + 1] != l);
         sa.check_max_iters = (q + 1 == seq.size() && l == 0 && p.stop_update_norm > 0.0);
-        if ((st = launch_solve_batch(p.precision, b->d_inst, n, sa, s)) != UPS_OK) return st;
+        if (mask)
+            st = launch_solve_batch_list(p.precision, b->d_inst, b->comp, b->comp_list, std::min(n, kListSolveBlocks),
+                                         sa, s);
+        else
+            st = launch_solve_batch(p.precision, b->d_inst, n, sa, s);
+        if (st != UPS_OK) return st;
     }
     a.level = 0;
     a.d_max2 = p.d_max[0] * p.d_max[0];
     a.tau2 = a.d_max2;
-    if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0],
-                               s)) != UPS_OK)
-        return st;
+    if (mask)
+        st = launch_icp_batch_list(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->comp, b->comp_list, b->comp_start,
+                                   n, a, std::min(b->total_tiles[0], kListBlocks), s);
+    else
+        st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0], s);
+    if (st != UPS_OK) return st;
     return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
 }
 
@@ -384,18 +410,35 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
     return register_batch_impl(b, init_d, nullptr, results_d, (hipStream_t)stream);
 }
 
-ups_status ups_register_batch_fallback(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
-                                       ups_icp_result *results_d, void *stream) {
+ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
+                                   const ups_icp_result *results_d, int32_t *count_d, void *stream) {
     UPS_REQUIRE(ctx && b, "null argument");
     UPS_REQUIRE(std::isfinite(min_inlier_ratio), "min_inlier_ratio must be finite");
+    ups_status st;
+    if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
+    if (count_d && (st = check_ptr(count_d, 4, "count")) != UPS_OK) return st;
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    return launch_fallback_plan(b->n, results_d, min_inlier_ratio, b->d_tile_start, b->mask, b->comp, b->comp_list,
+                                b->comp_start, count_d, (hipStream_t)stream);
+}
+
+ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result *results_d, void *stream) {
+    UPS_REQUIRE(ctx && b, "null argument");
     ups_status st;
     if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
     Guard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     hipStream_t s = (hipStream_t)stream;
-    if ((st = launch_fallback_mask(b->n, results_d, min_inlier_ratio, b->mask, s)) != UPS_OK) return st;
     if ((st = register_batch_impl(b, b->ident, b->mask, b->alt, s)) != UPS_OK) return st;
     return launch_fallback_merge(b->n, results_d, b->alt, b->mask, s);
+}
+
+ups_status ups_register_batch_fallback(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
+                                       ups_icp_result *results_d, void *stream) {
+    ups_status st = ups_batch_fallback_plan(ctx, b, min_inlier_ratio, results_d, nullptr, stream);
+    if (st != UPS_OK) return st;
+    return ups_batch_fallback_run(ctx, b, results_d, stream);
 }
 
 }  // extern "C"

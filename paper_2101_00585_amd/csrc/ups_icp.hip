@@ -467,6 +467,25 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ i
     icp_block<K, PREC, MODE, false>(insts[lo], a, b - tile_start[lo]);
 }
 
+// A subset of the batch (a Compact list): a fixed grid strides over the
+// subset's tiles, so the launch costs little when the subset is small.
+template <int K, int PREC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restrict__ insts,
+                                                           const Compact *__restrict__ hdr,
+                                                           const int *__restrict__ list,
+                                                           const int *__restrict__ start, StepArgs a) {
+    const int cnt = hdr->count, total = hdr->total[a.level];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = cnt;  // the last m with start[m] <= t
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (start[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        icp_block<K, PREC, MODE, false>(insts[list[lo]], a, t - start[lo]);
+    }
+}
+
 // Batch, between two Gauss-Newton launches: one block per registration
 // reduces the partials of the launch that just ran (if it processed the
 // registration), applies the update, and decides whether the next launch
@@ -474,23 +493,38 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ i
 // a.first_of_level: the next launch starts a new level; a.check_max_iters: it
 // was the last launch of level 0.
 template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_solve_batch(const Inst *__restrict__ insts, StepArgs a) {
+__device__ __forceinline__ void solve_block(const Inst &I, const StepArgs &a) {
     using Acc = AccOf<PREC>;
     __shared__ RegState S;
     __shared__ Acc rows[29][16];
     __shared__ Acc tot[32];
-    const Inst &I = insts[blockIdx.x];
     if (threadIdx.x == 0) S = I.state[0];
     __syncthreads();
     if (S.active && !S.stop) {
         reduce_partials<29, Acc>(I.partials, npartials_of(I.nblocks[a.prev_level]), rows, tot);
         if (threadIdx.x == 0) gn_step<Acc>(a, tot, S);
     }
-    if (threadIdx.x != 0) return;
-    if (a.first_of_level) S.level_active = 1;
-    if (a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
-    S.active = !S.stop && S.level_active;
-    I.state[0] = S;
+    if (threadIdx.x == 0) {
+        if (a.first_of_level) S.level_active = 1;
+        if (a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
+        S.active = !S.stop && S.level_active;
+        I.state[0] = S;
+    }
+    __syncthreads();  // S is reused when the caller loops
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_solve_batch(const Inst *__restrict__ insts, StepArgs a) {
+    solve_block<PREC>(insts[blockIdx.x], a);
+}
+
+// The registrations of a Compact list only, a small grid striding over them.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_solve_batch_list(const Inst *__restrict__ insts,
+                                                             const Compact *__restrict__ hdr,
+                                                             const int *__restrict__ list, StepArgs a) {
+    const int cnt = hdr->count;
+    for (int m = blockIdx.x; m < cnt; m += gridDim.x) solve_block<PREC>(insts[list[m]], a);
 }
 
 // One block: the evaluation partials -> result (quality at the final pose,
@@ -667,10 +701,55 @@ ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, 
     return UPS_OK;
 }
 
-__global__ void k_fallback_mask(int n, const ups_icp_result *__restrict__ res, double min_ratio,
-                                uint8_t *__restrict__ mask) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) mask[k] = res[k].inlier_ratio < min_ratio ? 1 : 0;
+// One block: mask[k] = (inlier ratio of result k < min_ratio), and the
+// Compact list of the masked registrations (block-wide prefix sums over
+// chunks of 256 registrations, in registration order).
+__global__ __launch_bounds__(256) void k_fallback_plan(int n, const ups_icp_result *__restrict__ res,
+                                                        double min_ratio, const int *__restrict__ tile_start,
+                                                        uint8_t *__restrict__ mask, Compact *__restrict__ hdr,
+                                                        int *__restrict__ list, int *__restrict__ start,
+                                                        int32_t *__restrict__ count) {
+    __shared__ int sc[2][5][256];
+    __shared__ int carry[5];
+    const int tid = threadIdx.x;
+    if (tid < 5) carry[tid] = 0;
+    if (tid < 4) start[tid * (n + 1)] = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += 256) {
+        const int k = c0 + tid;
+        int v[5] = {0, 0, 0, 0, 0};
+        if (k < n) {
+            v[0] = res[k].inlier_ratio < min_ratio ? 1 : 0;
+            mask[k] = (uint8_t)v[0];
+            if (v[0])
+                for (int l = 0; l < 4; l++) v[1 + l] = tile_start[l * (n + 1) + k + 1] - tile_start[l * (n + 1) + k];
+        }
+        // inclusive Hillis-Steele scans of the five quantities
+        int buf = 0;
+        for (int q = 0; q < 5; q++) sc[0][q][tid] = v[q];
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            for (int q = 0; q < 5; q++) {
+                const int x = sc[buf][q][tid] + (tid >= off ? sc[buf][q][tid - off] : 0);
+                sc[buf ^ 1][q][tid] = x;
+            }
+            buf ^= 1;
+            __syncthreads();
+        }
+        if (v[0]) {
+            const int m = carry[0] + sc[buf][0][tid] - 1;
+            list[m] = k;
+            for (int l = 0; l < 4; l++) start[l * (n + 1) + m + 1] = carry[1 + l] + sc[buf][1 + l][tid];
+        }
+        __syncthreads();
+        if (tid < 5) carry[tid] += sc[buf][tid][255];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        hdr->count = carry[0];
+        for (int l = 0; l < 4; l++) hdr->total[l] = carry[1 + l];
+        if (count) *count = carry[0];
+    }
 }
 
 // Where the fallback ran and ended with a lower truncated cost, its result
@@ -685,8 +764,10 @@ __global__ void k_fallback_merge(int n, ups_icp_result *__restrict__ res, const 
     }
 }
 
-ups_status launch_fallback_mask(int n, const ups_icp_result *res, double min_ratio, uint8_t *mask, hipStream_t s) {
-    hipLaunchKernelGGL(k_fallback_mask, dim3((n + 255) / 256), dim3(256), 0, s, n, res, min_ratio, mask);
+ups_status launch_fallback_plan(int n, const ups_icp_result *res, double min_ratio, const int *tile_start,
+                                uint8_t *mask, Compact *hdr, int *list, int *start, int32_t *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fallback_plan, dim3(1), dim3(256), 0, s, n, res, min_ratio, tile_start, mask, hdr, list,
+                       start, count);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
@@ -794,6 +875,26 @@ ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const 
     return UPS_OK;
 }
 
+template <int K, int PREC>
+static void launch_list_t(int mode, const Inst *insts, const Compact *hdr, const int *list, const int *start_l,
+                          const StepArgs &a, int blocks, hipStream_t s) {
+    if (mode == MODE_ITER)
+        hipLaunchKernelGGL((k_icp_batch_list<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, insts, hdr, list,
+                           start_l, a);
+    else
+        hipLaunchKernelGGL((k_icp_batch_list<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, insts, hdr, list,
+                           start_l, a);
+}
+
+ups_status launch_icp_batch_list(int K, int prec, int mode, const Inst *insts, const Compact *hdr, const int *list,
+                                 const int *start_l, int n, const StepArgs &a, int blocks, hipStream_t s) {
+    (void)n;
+    if (blocks <= 0) return UPS_OK;
+    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_list_t<KK, PP>(mode, insts, hdr, list, start_l, a, blocks, s)))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
 __global__ void k_activate_batch(const Inst *__restrict__ insts, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) insts[k].state[0].active = 1;
@@ -807,6 +908,14 @@ ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s) {
 
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s) {
     UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_solve_batch<PP>, dim3(n), dim3(kBlock), 0, s, insts, a))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
+                                   const StepArgs &a, hipStream_t s) {
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_solve_batch_list<PP>, dim3(blocks), dim3(kBlock), 0, s, insts, hdr,
+                                            list, a))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

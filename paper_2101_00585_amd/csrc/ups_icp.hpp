@@ -47,6 +47,14 @@ struct StepArgs {
     double stop_norm;
 };
 
+// A subset of a batch's registrations: list[m] for m < count, and per level
+// l the prefix table start[l][m] (m <= count) of their tile counts, whose
+// total is total[l].  Device memory: header, then list[n], then start[4][n+1].
+struct Compact {
+    int count;
+    int total[4];
+};
+
 int pick_k_single(int npix);
 ups_status launch_register(const Inst &I, const ups_pose *init, const ups_icp_params &p, hipStream_t s);
 ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
@@ -58,11 +66,16 @@ ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const 
                             const StepArgs &a, int blocks, hipStream_t s);
 ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s);
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
+ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
+                                   const StepArgs &a, hipStream_t s);
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
                                hipStream_t s);
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
                                 int total_pix, const uint8_t *mask, hipStream_t s);
-ups_status launch_fallback_mask(int n, const ups_icp_result *res, double min_ratio, uint8_t *mask, hipStream_t s);
+ups_status launch_fallback_plan(int n, const ups_icp_result *res, double min_ratio, const int *tile_start,
+                                uint8_t *mask, Compact *hdr, int *list, int *start, int32_t *count, hipStream_t s);
+ups_status launch_icp_batch_list(int K, int prec, int mode, const Inst *insts, const Compact *hdr, const int *list,
+                                 const int *start_l, int n, const StepArgs &a, int blocks, hipStream_t s);
 ups_status launch_fallback_merge(int n, ups_icp_result *res, const ups_icp_result *alt, const uint8_t *mask,
                                  hipStream_t s);
 __device__ __host__ inline int npartials_host(int nblocks) { return nblocks > 256 ? 1 : nblocks; }

@@ -322,13 +322,31 @@ class ProposedRegistration:
                         [it["kf_geom"] for it in items], [it["scan_geom"] for it in items])
         self.y = torch.empty((self.n, 6), dtype=torch.float32, device="cuda")
         self.poses = torch.empty((self.n, 12), dtype=torch.float64, device="cuda")
+        self.count = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     def run(self, results):
+        """The whole path, fallback launches always enqueued (capturable)."""
+        self.propose_and_register(results)
+        self.batch.fallback_run(results)
+        return results
+
+    def propose_and_register(self, results):
+        """Everything up to the fallback decision: network input, network,
+        poses, registration from them, and the fallback plan (the number of
+        registrations to rerun lands in ``self.count``)."""
         self.prop.input()
         self.prop.forward(self.n, None, self.y)
         self.prop.poses(self.y, self.poses)
         self.batch.register(self.poses, results)
-        self.batch.fallback(results, self.rho)
+        self.batch.fallback_plan(results, self.rho, self.count)
+        return results
+
+    def run_checked(self, results):
+        """propose_and_register, then the fallback only if some registration
+        needs it (one host read of the count)."""
+        self.propose_and_register(results)
+        if int(self.count.item()) > 0:
+            self.batch.fallback_run(results)
         return results
 
 

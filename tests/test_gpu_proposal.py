@@ -126,6 +126,19 @@ def test_fallback_only_where_flagged(arms, gpu_lib):
             assert np.array_equal(r["T"], s["T"])
 
 
+def test_checked_fallback_equals_the_full_path(arms, gpu_lib):
+    """Skipping the fallback launches when the plan flags nothing gives the
+    same results as always running them."""
+    import torch
+    pr = arms["pr"]
+    r2 = torch.zeros_like(arms["results"])
+    pr.run_checked(r2)
+    torch.cuda.synchronize()
+    got = gpu_lib.read_results(r2)
+    for a, b in zip(got, arms["proposed"]):
+        assert np.array_equal(a["T"], b["T"]) and a["status"] == b["status"]
+
+
 def test_proposed_path_replays_from_a_graph(arms):
     import torch
     pr, results = arms["pr"], arms["results"]
