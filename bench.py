@@ -43,6 +43,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM traffic of the roofline kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (KiB per launch), scaled by what the counters read for a 256 MiB
+# device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
+# figures and commands are in profiles/icp_iteration_*.md; they hold only for
+# the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.75, 1.0
+TRAFFIC_KIB = {"single": (2526.5, 64.17), "batch": (507008.6, 1966.0)}
+TRAFFIC_SRC_HASH = "566947962f762cf1"
+TRAFFIC_SRC = ("ups_icp.hip", "ups_icp.hpp", "ups_device.hpp", "ups_internal.hpp")
+
+
+def traffic_bytes(which):
+    """Scaled FETCH + WRITE bytes per launch, or None when the kernel sources
+    differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SRC:
+        with open(os.path.join(ROOT, "paper_2101_00585_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC_SRC_HASH:
+        return None
+    fetch, write = TRAFFIC_KIB[which]
+    return int(round((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024))
 LEVELS = 3
 ITERS = (10, 10, 10)
 N_BATCH = 256
@@ -243,7 +267,7 @@ def run_single(args, torch, ups, synth, W, stream):
     alg_bytes = BYTES_PER_PIXEL * npix + BYTES_PER_GATHER * gathers
     achieved = alg_bytes / (icp_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_bytes("single"),
                 "kernel": f"k_icp_one<2,{args.precision},iter> (level-0 Gauss-Newton launch, 128x1024)",
                 "launch_us": round(icp_us, 3), "algorithmic_bytes_per_launch": alg_bytes,
                 "note": "one 128x1024 registration: 4 MB per launch, cache-resident and latency bound"}
@@ -336,7 +360,7 @@ def run_batch(args, torch, ups, synth, W, stream):
         "pixels_per_thread_by_level": K[:LEVELS],
         "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_bytes("batch"),
                      "kernel": f"k_icp_batch<{K[0]},{args.precision},iter> (level-0 launch over all {N_BATCH})",
                      "launch_us": round(launch_us, 2), "algorithmic_bytes_per_launch": alg_bytes},
     }
