@@ -89,6 +89,7 @@ ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream
     d.rows = g->rows >> level;
     d.cols = g->cols >> level;
     d.stride = s;
+    d.lshift = level;
     d.el_top = (float)g->el_top;
     d.inv_d_el = (float)(1.0 / (g->d_el * s));
     d.az_scale = (float)((double)d.cols / (2.0 * M_PI));

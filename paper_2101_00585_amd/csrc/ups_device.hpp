@@ -19,6 +19,7 @@ constexpr int kBlock = 256;  // threads per workgroup for the per-pixel kernels
 struct DGeom {
     int rows, cols;       // at this level
     int stride;           // 2^level into the level-0 ray tables
+    int lshift;           // level (log2 of stride)
     float el_top, inv_d_el, az_scale;  // az_scale = cols / (2 pi)
     float r_min, r_max;
     int narrow;             // every row (with half a row of margin) lies within +-45 deg elevation
@@ -62,11 +63,13 @@ __device__ __forceinline__ float2 lds_uniform(const float2 *p, int idx) {
     return make_float2(v.x, v.y);
 }
 
-__device__ __forceinline__ bool range_ok(const DGeom &g, float r) { return r > g.r_min && r <= g.r_max; }
+// Validity tests combine their comparisons with non-short-circuit operators:
+// no branches, so that loads feeding them are not moved into conditional code.
+__device__ __forceinline__ bool range_ok(const DGeom &g, float r) { return (r > g.r_min) & (r <= g.r_max); }
 
-__device__ __forceinline__ bool normal_ok(float4 s) { return s.x != 0.f || s.y != 0.f || s.z != 0.f; }
+__device__ __forceinline__ bool normal_ok(float4 s) { return (s.x != 0.f) | (s.y != 0.f) | (s.z != 0.f); }
 
-__device__ __forceinline__ bool surfel_ok(const DGeom &g, float4 s) { return range_ok(g, s.w) && normal_ok(s); }
+__device__ __forceinline__ bool surfel_ok(const DGeom &g, float4 s) { return range_ok(g, s.w) & normal_ok(s); }
 
 __device__ __forceinline__ float3 ray(const DGeom &g, int i, int j) {
     const float2 e = ldg(g.lut_row, i * g.stride);
@@ -102,9 +105,10 @@ __device__ __forceinline__ float atan_unit(float a) {
 // pi - ..., and the sign of y.  Undefined for x = y = 0 (callers exclude it).
 __device__ __forceinline__ float atan2_fast(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const bool steep = ay > ax;
+    const float mx = steep ? ay : ax, mn = steep ? ax : ay;
     float r = atan_unit(mn * __builtin_amdgcn_rcpf(mx));
-    if (ay > ax) r = 1.57079632679489662f - r;
+    if (steep) r = 1.57079632679489662f - r;
     if (x < 0.f) r = 3.14159265358979324f - r;
     return copysignf(r, y);
 }
@@ -112,27 +116,31 @@ __device__ __forceinline__ float atan2_fast(float y, float x) {
 // Nearest pixel centre of the direction of q: i = floor(fi + 1/2),
 // j = floor(fj + 1/2) mod cols with fi = (el_top - el)/d_el and
 // fj = az cols / (2 pi), az in [0, 2 pi).  False for the origin and rows
-// outside [0, rows).
+// outside [0, rows).  Branch-free: pi and pj are computed (and meaningless)
+// whenever the result is false, so that callers can issue their loads
+// unconditionally.
 __device__ __forceinline__ bool project(const DGeom &g, float3 q, int &pi, int &pj) {
-    float rho = sqrtf(q.x * q.x + q.y * q.y);
-    if (rho == 0.f && q.z == 0.f) return false;
+    const float rho = __builtin_amdgcn_sqrtf(q.x * q.x + q.y * q.y);
+    bool ok;
     float el;
     if (g.narrow) {
         // the panorama lies within +-45 deg: steeper directions have no pixel
-        if (!(fabsf(q.z) < rho)) return false;
+        // (this also excludes the origin)
+        ok = fabsf(q.z) < rho;
         el = atan_unit(q.z * __builtin_amdgcn_rcpf(rho));
     } else {
+        ok = (rho != 0.f) | (q.z != 0.f);
         el = atan2_fast(q.z, rho);
     }
     float az = atan2_fast(q.y, q.x);
-    if (az < 0.f) az += kTwoPi;
-    float fi = floorf((g.el_top - el) * g.inv_d_el + 0.5f);
-    if (!(fi >= 0.f && fi < (float)g.rows)) return false;
+    az = az < 0.f ? az + kTwoPi : az;
+    const float fi = floorf((g.el_top - el) * g.inv_d_el + 0.5f);
+    ok = ok & (fi >= 0.f) & (fi < (float)g.rows);
     int j = (int)floorf(az * g.az_scale + 0.5f);
-    if (j >= g.cols) j -= g.cols;
+    j = j >= g.cols ? j - g.cols : j;
     pi = (int)fi;
     pj = j;
-    return true;
+    return ok;
 }
 
 struct Rt32 {
@@ -181,30 +189,32 @@ struct Gather {
     float2 e, a;  // keyframe ray tables (cos, sin) of the row and the column
 };
 
+// Branch-free: every lane issues its three loads (lanes without a pixel read
+// pixel 0) and carries kf_index = -1.
 __device__ __forceinline__ Gather scan_side(const DGeom &sg, float4 s2, float2 e, float2 ca, const DGeom &kg,
                                             const float4 *__restrict__ kf, const Rt32 &T) {
     Gather G;
-    G.kf_index = -1;
-    if (!surfel_ok(sg, s2)) return G;
+    const bool sok = surfel_ok(sg, s2);
     const float3 u = make_float3(e.x * ca.x, e.x * ca.y, e.y);
     const float3 p = make_float3(s2.w * u.x, s2.w * u.y, s2.w * u.z);
     G.q = transform(T, p);
     G.m = rotate(T, make_float3(s2.x, s2.y, s2.z));
     int ki, kj;
-    if (!project(kg, G.q, ki, kj)) return G;
-    G.kf_index = ki * kg.cols + kj;
-    G.s1 = ldg_u(kf, (uint32_t)G.kf_index);
-    G.e = ldg_u(kg.lut_row, (uint32_t)(ki * kg.stride));
-    G.a = ldg_u(kg.lut_col, (uint32_t)(kj * kg.stride));
+    const bool ok = project(kg, G.q, ki, kj) & sok;
+    ki = ok ? ki : 0;
+    kj = ok ? kj : 0;
+    const uint32_t idx = __umul24((uint32_t)ki, (uint32_t)kg.cols) + (uint32_t)kj;
+    G.kf_index = ok ? (int)idx : -1;
+    G.s1 = ldg_u(kf, idx);
+    G.e = ldg_u(kg.lut_row, (uint32_t)ki << kg.lshift);
+    G.a = ldg_u(kg.lut_col, (uint32_t)kj << kg.lshift);
     return G;
 }
 
 __device__ __forceinline__ void kf_side(const DGeom &kg, const Gather &G, float d_max2, float cos_theta_max,
                                         bool &inlier, float &r, float3 &n1) {
-    inlier = false;
-    r = 0.f;
-    n1 = make_float3(0.f, 0.f, 0.f);
-    if (G.kf_index < 0 || !surfel_ok(kg, G.s1)) return;
+    // branch-free up to the inlier decision: the gathered values are used on
+    // every path, so their loads stay where scan_side issued them
     float3 d;
     {
         // no FMA contraction: q - s1 must vanish exactly when the pose is the
@@ -215,10 +225,8 @@ __device__ __forceinline__ void kf_side(const DGeom &kg, const Gather &G, float 
         d = sub3(G.q, x1);
     }
     n1 = make_float3(G.s1.x, G.s1.y, G.s1.z);
-    if (!(dot3(d, d) <= d_max2)) return;
-    if (!(dot3(G.m, n1) >= cos_theta_max)) return;
-    inlier = true;
     r = dot3(d, n1);
+    inlier = (G.kf_index >= 0) & surfel_ok(kg, G.s1) & (dot3(d, d) <= d_max2) & (dot3(G.m, n1) >= cos_theta_max);
 }
 
 // ---- world-frame variant (precision study): points carried in world

@@ -74,22 +74,36 @@ struct ThreadAcc;
 // Compensated FP32 where it pays: the Gauss-Newton fixed point is where
 // J^T r vanishes, so J^T r (values 21..26), sum r^2 (27) and the truncated
 // cost (30) are Kahan-compensated; the 21 J^T J entries, whose rounding only
-// perturbs the step size, are plain FP32 sums; counts are exact.
+// perturbs the step size, are plain FP32 sums; counts are exact.  The
+// compensated values are summed plainly over a group of up to 4 pixels and
+// each group sum enters the Kahan sum (flush), which keeps the compensation
+// at a quarter of the per-pixel cost; a 4-term FP32 sum adds at most 3 ulp
+// of its terms' magnitude before compensation.
 template <int NV>
 struct ThreadAcc<UPS_PREC_KAHAN_F64, NV> {
-    float s[NV], c[8];
+    static constexpr int NC = NV > 30 ? 8 : 7;  // compensated values
+    float s[NV], c[NC], g[NC];
     static __device__ __forceinline__ constexpr int comp(int v) { return (v >= 21 && v < 28) ? v - 21 : (v == 30 ? 7 : -1); }
+    static __device__ __forceinline__ constexpr int value_of(int j) { return j < 7 ? 21 + j : 30; }
     __device__ __forceinline__ void zero() {
 #pragma unroll
         for (int v = 0; v < NV; v++) s[v] = 0.f;
 #pragma unroll
-        for (int v = 0; v < 8; v++) c[v] = 0.f;
+        for (int j = 0; j < NC; j++) c[j] = g[j] = 0.f;
     }
     __device__ __forceinline__ void add(int v, float x) {
-        if (comp(v) >= 0) kahan_add(s[v], c[comp(v)], x);
+        if (comp(v) >= 0) g[comp(v)] += x;
         else s[v] += x;
     }
     __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
+    // the group sums enter the compensated sums
+    __device__ __forceinline__ void flush() {
+#pragma unroll
+        for (int j = 0; j < NC; j++) {
+            kahan_add(s[value_of(j)], c[j], g[j]);
+            g[j] = 0.f;
+        }
+    }
     __device__ __forceinline__ double get(int v) const {
         return comp(v) >= 0 ? (double)s[v] - (double)c[comp(v)] : (double)s[v];
     }
@@ -104,6 +118,7 @@ struct ThreadAcc<UPS_PREC_F32, NV> {  // plain FP32
     }
     __device__ __forceinline__ void add(int v, float x) { s[v] += x; }
     __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
+    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ float get(int v) const { return s[v]; }
 };
 
@@ -117,6 +132,7 @@ struct ThreadAcc<UPS_PREC_F64, NV> {  // FP64 (callers add exact FP64 products)
     __device__ __forceinline__ void add(int v, double x) { s[v] += x; }
     __device__ __forceinline__ void fma(int v, double a, double b) { s[v] = ::fma(a, b, s[v]); }
     __device__ __forceinline__ void count(int v) { s[v] += 1.0; }
+    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ double get(int v) const { return s[v]; }
 };
 
@@ -346,7 +362,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     const int col_step = kBlock % sg.cols;
     int jn = (base + tid) % sg.cols;
     float4 nxt = ldg_u(scan, (uint32_t)min(base + tid, npix - 1));
-    float2 nxt_a = ldg_u(sg.lut_col, (uint32_t)(jn * sg.stride));
+    float2 nxt_a = ldg_u(sg.lut_col, (uint32_t)jn << sg.lshift);
     if (!FUSED) {
         if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
         if (MODE == MODE_EVAL && slot_in->skip) return;
@@ -391,46 +407,78 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     }
     ThreadAcc<PREC, NV> acc;
     acc.zero();
+    // pixels in pairs: both pixels' keyframe gathers are in flight before the
+    // first of them is consumed, and the next pair's scan loads behind them
+    constexpr int P = (K >= 2) ? 2 : 1;
+    float4 nx[P];
+    float2 na[P];
+    int jc[P];
+    nx[0] = nxt;
+    na[0] = nxt_a;
+    jc[0] = jn;
+#pragma unroll
+    for (int u = 1; u < P; u++) {
+        jc[u] = jc[u - 1] + col_step;
+        jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
+        nx[u] = ldg_u(scan, (uint32_t)min(base + u * kBlock + tid, npix - 1));
+        na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
+    }
     int pw = pw0;
-#pragma unroll 2
-    for (int k = 0; k < K; k++) {
-        // the 64 pixels of a wavefront lie in one row (cols is a multiple of 64)
+#pragma unroll 1
+    for (int k = 0; k < K; k += P) {
         if (pw >= npix) break;
-        const float4 s2 = (base + k * kBlock + tid < npix) ? nxt : make_float4(0.f, 0.f, 0.f, 0.f);
-        const int i = pw / sg.cols;
-        const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
-        Gather G;
-        if constexpr (WORLD) G = scan_side_world(sg, s2, e, nxt_a, kg, kf, T, Wk);
-        else G = scan_side(sg, s2, e, nxt_a, kg, kf, T);
-        // next pixel's scan loads go out behind this pixel's keyframe gathers
-        pw = __builtin_amdgcn_readfirstlane(pw + kBlock);
-        if (k + 1 < K) {
-            const int pn = base + (k + 1) * kBlock + tid;
-            jn += col_step;
-            jn = jn >= sg.cols ? jn - sg.cols : jn;
-            nxt = ldg_u(scan, (uint32_t)min(pn, npix - 1));
-            nxt_a = ldg_u(sg.lut_col, (uint32_t)(jn * sg.stride));
+        Gather G[P];
+        float sw[P];
+#pragma unroll
+        for (int u = 0; u < P; u++) {
+            const float4 s2 = make_float4(nx[u].x, nx[u].y, nx[u].z,
+                                          (base + (k + u) * kBlock + tid < npix) ? nx[u].w : 0.f);
+            sw[u] = s2.w;
+            const int i = min(pw + u * kBlock, npix - 1) / sg.cols;
+            const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
+            if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk);
+            else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T);
+            // keep the consumers of these gathers below the next pixel's scan side
+            __builtin_amdgcn_sched_barrier(0);
         }
-        bool inl;
-        float r;
-        float3 n1;
-        if constexpr (WORLD) kf_side_world(kg, G, Wk, a.d_max2, a.cos_theta, inl, r, n1);
-        else kf_side(kg, G, a.d_max2, a.cos_theta, inl, r, n1);
-        if (inl) {
-            Pair pr;
-            pr.inlier = true;
-            pr.r = r;
-            pr.q = G.q;
-            pr.n1 = n1;
-            add_terms<PREC, NV>(acc, pr);
-        }
-        if (MODE == MODE_EVAL) {
-            if (range_ok(sg, s2.w)) {
-                acc.count(29);
-                acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
+        {
+            const bool more = k + P < K;
+#pragma unroll
+            for (int u = 0; u < P; u++) {
+                jc[u] += more ? P * col_step : 0;
+                jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
+                jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
+                nx[u] = ldg_u(scan, (uint32_t)min(base + (more ? k + P + u : k + u) * kBlock + tid, npix - 1));
+                na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
             }
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < P; u++) {
+            bool inl;
+            float r;
+            float3 n1;
+            if constexpr (WORLD) kf_side_world(kg, G[u], Wk, a.d_max2, a.cos_theta, inl, r, n1);
+            else kf_side(kg, G[u], a.d_max2, a.cos_theta, inl, r, n1);
+            if (inl) {
+                Pair pr;
+                pr.inlier = true;
+                pr.r = r;
+                pr.q = G[u].q;
+                pr.n1 = n1;
+                add_terms<PREC, NV>(acc, pr);
+            }
+            if (MODE == MODE_EVAL) {
+                if (range_ok(sg, sw[u])) {
+                    acc.count(29);
+                    acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
+                }
+            }
+        }
+        if ((k & 3) == 4 - P) acc.flush();
+        pw = __builtin_amdgcn_readfirstlane(pw + P * kBlock);
     }
+    acc.flush();
 
     // ---- 2. block partial
     {

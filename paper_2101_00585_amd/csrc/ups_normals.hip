@@ -21,9 +21,10 @@ __device__ __forceinline__ float3 raw_normal(const DGeom &g, int i, int j, int i
     const float3 a = make_float3(ra * ua.x - pc.x, ra * ua.y - pc.y, ra * ua.z - pc.z);
     const float3 b = make_float3(rb * ub.x - pc.x, rb * ub.y - pc.y, rb * ub.z - pc.z);
     const float3 n = cross3(a, b);
-    const float nn = sqrtf(dot3(n, n));
-    if (!(nn > 1e-6f * sqrtf(dot3(a, a)) * sqrtf(dot3(b, b)))) return o;
-    const float s = (dot3(n, pc) > 0.f) ? -1.f / nn : 1.f / nn;
+    const float nn = __builtin_amdgcn_sqrtf(dot3(n, n));
+    if (!(nn > 1e-6f * __builtin_amdgcn_sqrtf(dot3(a, a) * dot3(b, b)))) return o;
+    const float inv = __builtin_amdgcn_rcpf(nn);
+    const float s = (dot3(n, pc) > 0.f) ? -inv : inv;
     return make_float3(n.x * s, n.y * s, n.z * s);
 }
 
@@ -68,7 +69,7 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
     const float kn = 2.f * kLog2e * inv_sigma_n2;
     const float cx = kn * c.x, cy = kn * c.y, cz = kn * c.z;
     // log2 e ((r_q - r_p) / (sigma_r r_p))^2 = (r_q sr - r_p sr)^2
-    const float sr = 1.2011224087864498f * inv_sigma_r / c.w;  // sqrt(log2 e) / (sigma_r r_p)
+    const float sr = 1.2011224087864498f * inv_sigma_r * __builtin_amdgcn_rcpf(c.w);  // sqrt(log2 e) / (sigma_r r_p)
     const float csr = -c.w * sr;
     float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
@@ -88,9 +89,9 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
             az = fmaf(w, q.z, az);
         }
     }
-    const float nn = sqrtf(ax * ax + ay * ay + az * az);
-    if (nn > 0.f) {
-        const float s = 1.f / nn;
+    const float nn2 = ax * ax + ay * ay + az * az;
+    if (nn2 > 0.f) {
+        const float s = __builtin_amdgcn_rsqf(nn2);
         o.x = ax * s;
         o.y = ay * s;
         o.z = az * s;
