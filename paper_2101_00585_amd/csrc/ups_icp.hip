@@ -424,61 +424,71 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
         na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
     }
     int pw = pw0;
-#pragma unroll 1
-    for (int k = 0; k < K; k += P) {
-        if (pw >= npix) break;
-        Gather G[P];
-        float sw[P];
+    // groups of up to 4 pixels (the Kahan group), two unrolled per trip so
+    // that the compensated sums need no register copies between trips
+    constexpr int GP = K < 4 ? K : 4;
+    bool done = false;
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += GP) {
 #pragma unroll
-        for (int u = 0; u < P; u++) {
-            const float4 s2 = make_float4(nx[u].x, nx[u].y, nx[u].z,
-                                          (base + (k + u) * kBlock + tid < npix) ? nx[u].w : 0.f);
-            sw[u] = s2.w;
-            const int i = min(pw + u * kBlock, npix - 1) / sg.cols;
-            const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
-            if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk);
-            else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T);
-            // keep the consumers of these gathers below the next pixel's scan side
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        {
-            const bool more = k + P < K;
+        for (int k = k0; k < k0 + GP; k += P) {
+            if (pw >= npix) {
+                done = true;
+                break;
+            }
+            Gather G[P];
+            float sw[P];
 #pragma unroll
             for (int u = 0; u < P; u++) {
-                jc[u] += more ? P * col_step : 0;
-                jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-                jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-                nx[u] = ldg_u(scan, (uint32_t)min(base + (more ? k + P + u : k + u) * kBlock + tid, npix - 1));
-                na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
+                const float4 s2 = make_float4(nx[u].x, nx[u].y, nx[u].z,
+                                              (base + (k + u) * kBlock + tid < npix) ? nx[u].w : 0.f);
+                sw[u] = s2.w;
+                const int i = min(pw + u * kBlock, npix - 1) / sg.cols;
+                const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
+                if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk);
+                else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T);
+                // keep the consumers of these gathers below the next pixel's scan side
+                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        __builtin_amdgcn_sched_barrier(0);
+            {
+                const bool more = k + P < K;
 #pragma unroll
-        for (int u = 0; u < P; u++) {
-            bool inl;
-            float r;
-            float3 n1;
-            if constexpr (WORLD) kf_side_world(kg, G[u], Wk, a.d_max2, a.cos_theta, inl, r, n1);
-            else kf_side(kg, G[u], a.d_max2, a.cos_theta, inl, r, n1);
-            if (inl) {
-                Pair pr;
-                pr.inlier = true;
-                pr.r = r;
-                pr.q = G[u].q;
-                pr.n1 = n1;
-                add_terms<PREC, NV>(acc, pr);
-            }
-            if (MODE == MODE_EVAL) {
-                if (range_ok(sg, sw[u])) {
-                    acc.count(29);
-                    acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
+                for (int u = 0; u < P; u++) {
+                    jc[u] += more ? P * col_step : 0;
+                    jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
+                    jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
+                    nx[u] = ldg_u(scan, (uint32_t)min(base + (more ? k + P + u : k + u) * kBlock + tid, npix - 1));
+                    na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < P; u++) {
+                bool inl;
+                float r;
+                float3 n1;
+                if constexpr (WORLD) kf_side_world(kg, G[u], Wk, a.d_max2, a.cos_theta, inl, r, n1);
+                else kf_side(kg, G[u], a.d_max2, a.cos_theta, inl, r, n1);
+                if (inl) {
+                    Pair pr;
+                    pr.inlier = true;
+                    pr.r = r;
+                    pr.q = G[u].q;
+                    pr.n1 = n1;
+                    add_terms<PREC, NV>(acc, pr);
+                }
+                if (MODE == MODE_EVAL) {
+                    if (range_ok(sg, sw[u])) {
+                        acc.count(29);
+                        acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
+                    }
+                }
+            }
+            pw = __builtin_amdgcn_readfirstlane(pw + P * kBlock);
         }
-        if ((k & 3) == 4 - P) acc.flush();
-        pw = __builtin_amdgcn_readfirstlane(pw + P * kBlock);
+        acc.flush();
+        if (done) break;
     }
-    acc.flush();
 
     // ---- 2. block partial
     {
