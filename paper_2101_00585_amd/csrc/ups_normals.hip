@@ -44,7 +44,11 @@ __global__ __launch_bounds__(kBlock) void k_normals_raw(DGeom g, const float *__
     out[p] = make_float4(n.x, n.y, n.z, range_ok(g, rc) ? rc : 0.f);
 }
 
-constexpr int kTileW = 64, kTileH = 4;
+// Output tiles of the a-trous passes: 64 pixels wide, TH rows high, TH / 4
+// rows per thread.  Batches use 16 rows (the halo of recomputed raw normals
+// and of staged neighbours shrinks with the tile's height); a single panorama
+// uses 4 rows, which gives it enough workgroups to fill the GPU.
+constexpr int kTileW = 64, kTileHBatch = 16, kTileHOne = 4;
 
 // One a-trous output from an LDS surfel tile of row pitch LW whose pixel
 // (ly, lx) is the output (ly + 2 step, lx + 2 step) of the tile: 5x5 B3-spline
@@ -99,10 +103,11 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
     return o;
 }
 
-// One a-trous level with taps spaced `step` for the 4 x 64 output tile at
-// (x0, y0): the block stages the (4 + 4 step) x (64 + 4 step) surfel tile
-// around it in LDS (rows outside the image empty, columns wrapped), one output
-// per thread.
+// One a-trous level with taps spaced `step` for the 16 x 64 output tile at
+// (x0, y0): the block stages the (16 + 4 step) x (64 + 4 step) surfel tile
+// around it in LDS (rows outside the image empty, columns wrapped), four
+// outputs per thread.
+template <int kTileH>
 __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__restrict__ in, float4 *__restrict__ out,
                                             int x0, int y0, int step, float inv_sigma_r, float inv_sigma_n2,
                                             float4 *tile) {
@@ -118,28 +123,31 @@ __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__rest
         tile[idx] = v;
     }
     __syncthreads();
-    const int tx = threadIdx.x & (kTileW - 1), ty = threadIdx.x / kTileW;
-    const int gy = y0 + ty;
-    if (gy >= g.rows) return;
-    out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, step, inv_sigma_r, inv_sigma_n2);
+    const int tx = threadIdx.x & (kTileW - 1);
+    for (int ty = threadIdx.x / kTileW; ty < kTileH; ty += kBlock / kTileW) {
+        const int gy = y0 + ty;
+        if (gy >= g.rows) break;
+        out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, step, inv_sigma_r, inv_sigma_n2);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__restrict__ in, float4 *__restrict__ out,
                                                    int step, float inv_sigma_r, float inv_sigma_n2) {
     extern __shared__ float4 tile[];
-    atrous_tile(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileH, step, inv_sigma_r, inv_sigma_n2, tile);
+    atrous_tile<kTileHOne>(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, step, inv_sigma_r, inv_sigma_n2,
+                           tile);
 }
 
 // Raw normals and the first a-trous level (step 1) in one pass: the block
-// stages the ranges of its 4 x 64 outputs plus a 2-pixel halo (and the
+// stages the ranges of its 16 x 64 outputs plus a 2-pixel halo (and the
 // neighbour row/column the cross products need), computes the raw normals of
-// the 8 x 68 halo tile into LDS, then filters.
-constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
-constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
-
+// the 20 x 68 halo tile into LDS, then filters.
+template <int kTileH>
 __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float *__restrict__ depth,
                                                     float4 *__restrict__ out, int x0, int y0, float max_rel_jump,
                                                     float inv_sigma_r, float inv_sigma_n2) {
+    constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
+    constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
     __shared__ float rng[kDH][kDW];
     __shared__ float4 raw[kFH * kFW];
     // ranges of rows y0-3 .. y0+kTileH+2 and columns x0-2 .. x0+kTileW+2
@@ -169,17 +177,19 @@ __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float 
         raw[idx] = v;
     }
     __syncthreads();
-    const int tx = threadIdx.x & (kTileW - 1), ty = threadIdx.x / kTileW;
-    const int gy = y0 + ty;
-    if (gy >= g.rows) return;
-    out[gy * g.cols + x0 + tx] = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
+    const int tx = threadIdx.x & (kTileW - 1);
+    for (int ty = threadIdx.x / kTileW; ty < kTileH; ty += kBlock / kTileW) {
+        const int gy = y0 + ty;
+        if (gy >= g.rows) break;
+        out[gy * g.cols + x0 + tx] = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float *__restrict__ depth,
                                                            float4 *__restrict__ out, float max_rel_jump,
                                                            float inv_sigma_r, float inv_sigma_n2) {
-    normals_atrous_tile(g, depth, out, blockIdx.x * kTileW, blockIdx.y * kTileH, max_rel_jump, inv_sigma_r,
-                        inv_sigma_n2);
+    normals_atrous_tile<kTileHOne>(g, depth, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, max_rel_jump,
+                                   inv_sigma_r, inv_sigma_n2);
 }
 
 // ---- batched: block -> (image, tile) through the prefix table of tile counts
@@ -202,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *
     const NormImg &im = imgs[k];
     const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
-    normals_atrous_tile(im.g, im.depth, out_tmp ? im.tmp : im.out, bx * kTileW, by * kTileH, max_rel_jump,
-                        inv_sigma_r, inv_sigma_n2);
+    normals_atrous_tile<kTileHBatch>(im.g, im.depth, out_tmp ? im.tmp : im.out, bx * kTileW, by * kTileHBatch,
+                                     max_rel_jump, inv_sigma_r, inv_sigma_n2);
 }
 
 __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restrict__ imgs,
@@ -214,12 +224,12 @@ __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restri
     const NormImg &im = imgs[k];
     const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
-    atrous_tile(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW, by * kTileH, step,
-                inv_sigma_r, inv_sigma_n2, tile);
+    atrous_tile<kTileHBatch>(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW,
+                             by * kTileHBatch, step, inv_sigma_r, inv_sigma_n2, tile);
 }
 
-// Tiles of a panorama in the a-trous launches.
-int normal_tiles(const DGeom &g) { return (g.cols / kTileW) * ((g.rows + kTileH - 1) / kTileH); }
+// Tiles of a panorama in the batched a-trous launches.
+int normal_tiles(const DGeom &g) { return (g.cols / kTileW) * ((g.rows + kTileHBatch - 1) / kTileHBatch); }
 
 ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
                                 const ups_normal_params &p, hipStream_t s) {
@@ -239,7 +249,7 @@ ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int 
     UPS_CHECK_HIP(hipGetLastError());
     for (int l = 1; l < L; l++) {
         const int step = 1 << l;
-        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileH + 4 * step) * sizeof(float4);
+        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileHBatch + 4 * step) * sizeof(float4);
         hipLaunchKernelGGL(k_atrous_batch, dim3(total_tiles), dim3(kBlock), lds, s, imgs, tile_start, n, in_tmp, step,
                            inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
@@ -259,7 +269,7 @@ ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, 
         UPS_CHECK_HIP(hipGetLastError());
         return UPS_OK;
     }
-    const dim3 grid(g.cols / kTileW, (g.rows + kTileH - 1) / kTileH);
+    const dim3 grid(g.cols / kTileW, (g.rows + kTileHOne - 1) / kTileHOne);
     // ping-pong so that the last level writes `surfel`
     float4 *bufs[2] = {surfel, ctx->tmp_surfel};
     float4 *dst = bufs[(L - 1) % 2];
@@ -269,7 +279,7 @@ ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, 
     for (int l = 1; l < L; l++) {
         dst = bufs[(L - 1 - l) % 2];
         const int step = 1 << l;
-        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileH + 4 * step) * sizeof(float4);
+        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileHOne + 4 * step) * sizeof(float4);
         hipLaunchKernelGGL(k_atrous, grid, dim3(kBlock), lds, s, g, src, dst, step, inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         src = dst;
