@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.75, 1.0
-TRAFFIC_KIB = {"single": (2526.5, 64.17), "batch": (507008.6, 1966.0)}
-TRAFFIC_SRC_HASH = "566947962f762cf1"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
+TRAFFIC_KIB = {"single": (2519.21, 64.17), "batch": (498164.42, 983.0)}
+TRAFFIC_SRC_HASH = "404e3fe92569c436"
 TRAFFIC_SRC = ("ups_icp.hip", "ups_icp.hpp", "ups_device.hpp", "ups_internal.hpp")
 
 
