@@ -458,7 +458,13 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
     init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
     r_plain = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
     r_prop = torch.zeros_like(r_plain)
+    r_grid = torch.zeros_like(r_plain)
     pr = P.ProposedRegistration(ctx, prop, batch, items)
+    # the paper's loop-closure start: 324 candidates scored at pyramid level 2
+    gp = ups.GridParams()
+    g_scores = torch.empty((n, gp.n_yaw * gp.n_xy * gp.n_xy), dtype=torch.int32, device=dev)
+    g_best = torch.empty((n, 12), dtype=torch.float64, device=dev)
+    g_bsc = torch.empty(n, dtype=torch.int32, device=dev)
 
     def plain():
         batch.normals()
@@ -467,6 +473,11 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
     def learned():
         batch.normals()
         pr.propose_and_register(r_prop)
+
+    def grid():
+        batch.normals()
+        batch.grid_search(gp, init, g_scores, g_best, g_bsc)
+        batch.register(g_best, r_grid)
 
     plain()
     torch.cuda.synchronize()
@@ -481,20 +492,28 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
             g2.replay()
     torch.cuda.synchronize()
     res_l = ups.read_results(r_prop)
-    s_p, s_l = _successes(res_p, pairs, synth), _successes(res_l, pairs, synth)
+    grid()
+    torch.cuda.synchronize()
+    res_g = ups.read_results(r_grid)
+    ms_g = time_graph(torch, capture(torch, stream, grid), stream, args.batch_steps)
+    s_p, s_l, s_g = (_successes(r, pairs, synth) for r in (res_p, res_l, res_g))
 
     def px_it(res):
         return int(sum(sum(r["level_iters"][l] * (p["geom"].rows >> l) * (p["geom"].cols >> l) for l in range(LEVELS))
                        for r, p in zip(res, pairs)))
 
     log(f"motions up to {max_deg:.0f} deg / 2 m: success identity {s_p.sum()}/{n} in {ms_p:.3f} ms, "
-        f"proposal {s_l.sum()}/{n} in {ms_l:.3f} ms")
+        f"proposal {s_l.sum()}/{n} in {ms_l:.3f} ms, grid search {s_g.sum()}/{n} in {ms_g:.3f} ms")
     batch.close()
     return {"workload": f"{n} held-out pairs, batch sizes and scenes, motions up to {max_deg:.0f} deg / 2 m",
             "pixel_iterations_identity_start": px_it(res_p), "pixel_iterations_proposal_start": px_it(res_l),
             "success_within_1deg_5cm_identity_start": int(s_p.sum()),
             "success_within_1deg_5cm_proposal_start": int(s_l.sum()),
             "ms_per_batch_identity_start": round(ms_p, 4), "ms_per_batch_proposal_start": round(ms_l, 4),
+            "success_within_1deg_5cm_grid_search_start": int(s_g.sum()),
+            "ms_per_batch_grid_search_start": round(ms_g, 4),
+            "grid_search": f"{gp.n_yaw * gp.n_xy * gp.n_xy} candidates (yaw every {360 // gp.n_yaw} deg x "
+                           f"{gp.n_xy}x{gp.n_xy} translations {gp.xy_step} m apart) scored at pyramid level {gp.level}",
             "fallbacks_used": int(sum(r["status"] == 4 for r in res_l)), "n": n,
             "pose_error_vs_truth_identity_start": _errors(res_p, pairs, synth),
             "pose_error_vs_truth_proposal_start": _errors(res_l, pairs, synth)}

@@ -299,6 +299,28 @@ ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_in
                                    const ups_icp_result *results_d, int32_t *count_d, void *stream);
 ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result *results_d, void *stream);
 
+/* Loop-closure grid search (Section III-C): for every registration k of the
+ * batch, score the candidate transforms base_d[k] * G_c by a low-resolution
+ * projective alignment check -- the number of Omega inliers (thresholds
+ * d_max, cos_theta_max) of the scan's pyramid level `level` against the
+ * keyframe's -- and write the best candidate (most inliers, the lowest c among
+ * equals) to best_d[k] and its score to best_score_d[k] (may be NULL).
+ * Candidates c = (a * n_xy + u) * n_xy + v for a < n_yaw, u, v < n_xy:
+ * G_c = (Rz(2 pi a / n_yaw), ((u - h) xy_step, (v - h) xy_step, 0)),
+ * h = (n_xy - 1) / 2.  scores_d: caller-owned int32 [n][C] workspace, C =
+ * n_yaw n_xy^2 <= 65535, left holding every candidate's score.  Builds the
+ * batch's pyramids from the level-0 surfel images first; enqueues only
+ * kernels.  The best poses can start ups_register_batch. */
+typedef struct {
+    int32_t level;
+    int32_t n_yaw, n_xy;
+    float xy_step;
+    float d_max, cos_theta_max;
+} ups_grid_params;
+
+ups_status ups_batch_grid_search(ups_context *ctx, ups_batch *b, const ups_grid_params *p, const ups_pose *base_d,
+                                  int32_t *scores_d, ups_pose *best_d, int32_t *best_score_d, void *stream);
+
 /* Autotune the pixels per thread of batch launches for this device: times the
  * Gauss-Newton launch at 1, 2, 4, ..., 64 pixels per thread on synthetic
  * batches of each lidar panorama size (16x128 ... 128x2048) and keeps the

@@ -115,6 +115,7 @@ def load():
         "ups_register_batch_fallback": [_P, _P, ctypes.c_double, _P, _P],
         "ups_batch_fallback_plan": [_P, _P, ctypes.c_double, _P, _P, _P],
         "ups_batch_fallback_run": [_P, _P, _P, _P],
+        "ups_batch_grid_search": [_P, _P, _P, _P, _P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
         "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
@@ -442,6 +443,29 @@ def autotune(ctx: Context, cache_path: str | None = None):
     _check(_LIB.ups_autotune(ctx.handle, cache_path.encode() if cache_path else None))
 
 
+class ups_grid_params(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("n_yaw", ctypes.c_int32), ("n_xy", ctypes.c_int32),
+                ("xy_step", ctypes.c_float), ("d_max", ctypes.c_float), ("cos_theta_max", ctypes.c_float)]
+
+
+@dataclass
+class GridParams:
+    """Loop-closure grid search: pyramid level scored, yaw samples over the
+    turn, translation samples per axis and their spacing (m), Omega
+    thresholds of the check.  The default is 36 x 3 x 3 = 324 candidates at
+    level 2 with the level-2 registration gate."""
+    level: int = 2
+    n_yaw: int = 36
+    n_xy: int = 3
+    xy_step: float = 1.0
+    d_max: float = 2.0
+    cos_theta_max: float = math.cos(math.radians(30.0))
+
+    def c(self) -> ups_grid_params:
+        return ups_grid_params(int(self.level), int(self.n_yaw), int(self.n_xy), float(self.xy_step),
+                               float(self.d_max), float(self.cos_theta_max))
+
+
 class Batch:
     """A planned batch of registrations.  ``items``: dicts with ``scan_geom``,
     ``kf_geom``, device ``scan_surfel`` / ``kf_surfel`` float32 [rows, cols, 4]
@@ -495,6 +519,29 @@ class Batch:
         _check(_LIB.ups_batch_fallback_run(self.ctx.handle, self._h, _dev_ptr(results, torch.uint8, "results"),
                                            _stream()))
         return results
+
+    def grid_search(self, params: "GridParams | None" = None, base=None, scores=None, best=None, best_score=None):
+        """Loop-closure grid search: returns (best poses [n, 12] FP64, best
+        scores [n] int32, all scores [n, C] int32) as device tensors."""
+        torch = _torch()
+        gp = params or GridParams()
+        C = gp.n_yaw * gp.n_xy * gp.n_xy
+        if base is None:
+            base = torch.stack([pose_tensor(np.eye(4)) for _ in range(self.n)])
+        if scores is None:
+            scores = torch.empty((self.n, C), dtype=torch.int32, device="cuda")
+        if best is None:
+            best = torch.empty((self.n, 12), dtype=torch.float64, device="cuda")
+        if best_score is None:
+            best_score = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        c = gp.c()
+        _check(_LIB.ups_batch_grid_search(self.ctx.handle, self._h, ctypes.byref(c),
+                                          _dev_ptr(base, torch.float64, "base poses"),
+                                          _dev_ptr(scores, torch.int32, "scores"),
+                                          _dev_ptr(best, torch.float64, "best poses"),
+                                          _dev_ptr(best_score, torch.int32, "best scores"), _stream()))
+        self._grid_keep = base
+        return best, best_score, scores
 
     def pixels_per_thread(self):
         out = (ctypes.c_int32 * 4)()

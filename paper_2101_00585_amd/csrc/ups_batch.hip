@@ -410,6 +410,37 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
     return register_batch_impl(b, init_d, nullptr, results_d, (hipStream_t)stream);
 }
 
+ups_status ups_batch_grid_search(ups_context *ctx, ups_batch *b, const ups_grid_params *gp, const ups_pose *base_d,
+                                  int32_t *scores_d, ups_pose *best_d, int32_t *best_score_d, void *stream) {
+    UPS_REQUIRE(ctx && b && gp, "null argument");
+    UPS_REQUIRE(gp->level >= 0 && gp->level < b->p.levels, "grid level must be one of the batch's pyramid levels");
+    UPS_REQUIRE(gp->n_yaw >= 1 && gp->n_xy >= 1 && (int64_t)gp->n_yaw * gp->n_xy * gp->n_xy <= 65535,
+                "need n_yaw, n_xy >= 1 and at most 65535 candidates");
+    UPS_REQUIRE(std::isfinite(gp->xy_step) && gp->xy_step >= 0.f, "xy_step must be finite and >= 0");
+    UPS_REQUIRE(gp->d_max > 0.f && std::isfinite(gp->cos_theta_max), "invalid Omega thresholds");
+    ups_status st;
+    if ((st = check_ptr(base_d, 8, "base poses")) != UPS_OK) return st;
+    if ((st = check_ptr(scores_d, 4, "scores")) != UPS_OK) return st;
+    if ((st = check_ptr(best_d, 8, "best poses")) != UPS_OK) return st;
+    if (best_score_d && (st = check_ptr(best_score_d, 4, "best scores")) != UPS_OK) return st;
+    Guard dg(ctx->device);
+    UPS_CHECK_HIP(dg.err);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = b->n, l = gp->level;
+    if (l > 0 && (st = launch_build_pyramids(b->d_inst, n, b->p.levels, b->d_pre_start, b->total_pre, s)) != UPS_OK)
+        return st;
+    GridArgs g;
+    g.level = l;
+    g.n_yaw = gp->n_yaw;
+    g.n_xy = gp->n_xy;
+    g.C = gp->n_yaw * gp->n_xy * gp->n_xy;
+    g.xy_step = gp->xy_step;
+    g.d_max2 = gp->d_max * gp->d_max;
+    g.cos_theta = gp->cos_theta_max;
+    return launch_grid_search(b->d_inst, b->d_tile_start + l * (n + 1), n, b->K[l], b->total_tiles[l], base_d, g,
+                              scores_d, best_d, best_score_d, s);
+}
+
 ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_inlier_ratio,
                                    const ups_icp_result *results_d, int32_t *count_d, void *stream) {
     UPS_REQUIRE(ctx && b, "null argument");

@@ -759,6 +759,17 @@ ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, 
     return UPS_OK;
 }
 
+// The pyramids alone (no registration state is touched).
+ups_status launch_build_pyramids(const Inst *insts, int n, int levels, const int *pix_start, int total_pix,
+                                 hipStream_t s) {
+    const int pb = (total_pix + kBlock - 1) / kBlock;
+    if (pb == 0) return UPS_OK;
+    hipLaunchKernelGGL(k_prepare_batch, dim3(pb), dim3(kBlock), 0, s, insts, (const ups_pose *)nullptr, n, levels, 0,
+                       pix_start, (const uint8_t *)nullptr);
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
 // One block: mask[k] = (inlier ratio of result k < min_ratio), and the
 // Compact list of the masked registrations (block-wide prefix sums over
 // chunks of 256 registrations, in registration order).

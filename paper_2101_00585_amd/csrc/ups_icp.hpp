@@ -55,7 +55,18 @@ struct Compact {
     int total[4];
 };
 
+// Loop-closure grid search over candidate transforms (see ups_grid.hip).
+struct GridArgs {
+    int level, n_yaw, n_xy, C;
+    float xy_step, d_max2, cos_theta;
+};
+
 int pick_k_single(int npix);
+ups_status launch_grid_search(const Inst *insts, const int *tile_start_l, int n, int K, int tiles,
+                              const ups_pose *base, const GridArgs &g, int *scores, ups_pose *best, int *best_score,
+                              hipStream_t s);
+ups_status launch_build_pyramids(const Inst *insts, int n, int levels, const int *pix_start, int total_pix,
+                                 hipStream_t s);
 ups_status launch_register(const Inst &I, const ups_pose *init, const ups_icp_params &p, hipStream_t s);
 ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
                                         const ups_pose *T, const ups_pose &world_kf, float d_max, float cos_theta,

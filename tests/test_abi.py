@@ -41,6 +41,8 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(ups.ups_icp_params) == 4 + 16 + 16 + 4 + 8 + 4 + 4
     assert ups.RESULT_BYTES == 96 + 24 + 16 + 8 + 16 + 21 * 8 + 6 * 8 + 8
     assert ups.NEQ_BYTES == 21 * 8 + 6 * 8 + 8 + 16
+    assert ctypes.sizeof(ups.ups_grid_params) == 6 * 4
+    assert ctypes.sizeof(ups.ups_range_image) == 8 + 3 * 4 + 2 * 4 + 4  # pointer, 3 ints, 2 floats, padding
 
 
 def test_last_error_without_gpu(lib):

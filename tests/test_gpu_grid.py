@@ -1,0 +1,134 @@
+"""Loop-closure grid search (Section III-C): candidate transforms scored by
+the number of Omega inliers at a coarse pyramid level, the best one promoted
+to the full-resolution batched registration.
+
+Scores are compared with the FP64 oracle's inlier counts at the same
+candidate poses on its own surfel images (normals and pyramid computed by
+the oracle from the same depth); the promoted registrations are compared
+with identity-started ones on pairs with relative yaw up to 90 deg."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BATCH_PARAMS = dict(levels=3, iters=(10, 10, 10), stop_update_norm=1e-6)
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _candidate(c, n_yaw, n_xy, step):
+    """G_c written out from its definition (FP64, 4x4)."""
+    a, u, v = c // (n_xy * n_xy), (c // n_xy) % n_xy, c % n_xy
+    h = (n_xy - 1) / 2
+    return synth.se3(synth.rot_z(2 * math.pi * a / n_yaw), [(u - h) * step, (v - h) * step, 0.0])
+
+
+def _items(pairs):
+    import torch
+    items = []
+    for p in pairs:
+        g = p["geom"]
+        items.append(dict(scan_geom=g, kf_geom=g, scan_depth=_t(p["scan"]), kf_depth=_t(p["kf"]),
+                          scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda"),
+                          kf_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device="cuda")))
+    return items
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0, max_pixels=128 * 2048, max_batch=64, max_batch_pixels=64 * 128 * 2048)
+    yield c
+    c.close()
+
+
+def test_scores_match_oracle_counts(gpu_lib, ctx):
+    pairs = [W.batch_pair(k, base_seed=5_000_000, max_angle=math.radians(90.0), size=(64, 512)) for k in range(2)]
+    gp = gpu_lib.GridParams(level=2, n_yaw=12, n_xy=3, xy_step=1.0, d_max=2.0)
+    items = _items(pairs)
+    b = gpu_lib.Batch(ctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    best, best_score, scores = b.grid_search(gp)
+    scores = scores.cpu().numpy()
+    best = best.cpu().numpy()
+    best_score = best_score.cpu().numpy()
+    C = 12 * 9
+    for k, p in enumerate(pairs):
+        g = p["geom"]
+        gl = g.level(2)
+        sl = O.pyramid_level(g, O.panorama_normals(g, p["scan"]), 2)
+        kl = O.pyramid_level(g, O.panorama_normals(g, p["kf"]), 2)
+        valid = int((sl[..., 3] > 0).sum())
+        ref = np.array([int(O.correspondences(gl, sl, gl, kl, _candidate(c, 12, 3, 1.0), 2.0,
+                                              math.cos(math.radians(30.0)))[1].sum()) for c in range(C)])
+        tol = max(2, int(0.01 * valid))
+        assert np.abs(scores[k] - ref).max() <= tol, (k, np.abs(scores[k] - ref).max(), tol)
+        c_best = int(np.argmax(scores[k]))
+        assert best_score[k] == scores[k].max() and np.argmax(scores[k] == scores[k].max()) == c_best
+        assert ref[c_best] >= ref.max() - 2 * tol
+        T = np.eye(4)
+        T[:3, :3] = best[k, :9].reshape(3, 3)
+        T[:3, 3] = best[k, 9:]
+        np.testing.assert_allclose(T, _candidate(c_best, 12, 3, 1.0), atol=1e-12)
+    b.close()
+
+
+def test_grid_start_beats_identity_at_large_yaw(gpu_lib, ctx):
+    import torch
+    n = 32
+    pairs = [W.batch_pair(k, base_seed=5_100_000, max_angle=math.radians(90.0), max_trans=2.0) for k in range(n)]
+    items = _items(pairs)
+    b = gpu_lib.Batch(ctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    plain = gpu_lib.read_results(b.register([np.eye(4)] * n))
+    best, _, _ = b.grid_search(gpu_lib.GridParams())
+    grid = gpu_lib.read_results(b.register(best))
+    torch.cuda.synchronize()
+
+    def ok(res):
+        return np.array([synth.pose_error(r["T"], p["T_gt"])[0] < math.radians(1.0)
+                         and synth.pose_error(r["T"], p["T_gt"])[1] < 0.05 for r, p in zip(res, pairs)])
+
+    s_plain, s_grid = ok(plain), ok(grid)
+    print(f"\ngrid search: success identity start {s_plain.sum()}/{n}, grid start {s_grid.sum()}/{n}")
+    assert s_grid.sum() >= s_plain.sum() + 0.1 * n
+    assert s_grid.mean() >= 0.8
+    b.close()
+
+
+def test_grid_search_replays_from_a_graph(gpu_lib, ctx):
+    import torch
+    pairs = [W.batch_pair(k, base_seed=5_200_000, max_angle=math.radians(60.0), size=(64, 512)) for k in range(4)]
+    items = _items(pairs)
+    b = gpu_lib.Batch(ctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    gp = gpu_lib.GridParams(n_yaw=18)
+    base = torch.stack([gpu_lib.pose_tensor(np.eye(4)) for _ in items])
+    scores = torch.empty((4, 18 * 9), dtype=torch.int32, device="cuda")
+    best = torch.empty((4, 12), dtype=torch.float64, device="cuda")
+    bsc = torch.empty(4, dtype=torch.int32, device="cuda")
+    b.normals()
+    b.grid_search(gp, base, scores, best, bsc)
+    torch.cuda.synchronize()
+    eager = (scores.cpu().numpy().copy(), best.cpu().numpy().copy())
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        b.grid_search(gp, base, scores, best, bsc)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            b.grid_search(gp, base, scores, best, bsc)
+    for _ in range(2):
+        scores.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(scores.cpu().numpy(), eager[0]) and np.array_equal(best.cpu().numpy(), eager[1])
+    b.close()
