@@ -52,7 +52,8 @@ def _lib():
             build()
         _LIB = ctypes.CDLL(so)
         for name in ("orc_project", "orc_raw_normals", "orc_atrous", "orc_panorama_normals", "orc_pyramid_level",
-                     "orc_residuals", "orc_normal_equations", "orc_solve6", "orc_register", "orc_fuse"):
+                     "orc_residuals", "orc_normal_equations", "orc_normal_equations_irls", "orc_solve6",
+                     "orc_register", "orc_fuse"):
             getattr(_LIB, name).restype = ctypes.c_int
     return _LIB
 
@@ -74,7 +75,7 @@ class _NormalParams(ctypes.Structure):
 class _IcpParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("d_max", ctypes.c_double * 4),
                 ("cos_theta_max", ctypes.c_double), ("stop_update_norm", ctypes.c_double),
-                ("min_inliers", ctypes.c_int32)]
+                ("min_inliers", ctypes.c_int32), ("irls_delta", ctypes.c_double)]
 
 
 class _IcpResult(ctypes.Structure):
@@ -106,19 +107,22 @@ class NormalParams:
 @dataclass
 class IcpParams:
     """Readings for Section III-B: d_max = 0.5 m at level 0 doubling per
-    coarser level, theta_max = 30 deg, at least 64 inliers."""
+    coarser level, theta_max = 30 deg, at least 64 inliers.  ``irls_delta``
+    0 minimises the squared residuals; > 0 minimises the absolute residuals of
+    Equation 1 by reweighting with 1 / max(|r|, irls_delta)."""
     levels: int = 1
     iters: tuple = (20, 0, 0, 0)
     d_max: tuple = (0.5, 1.0, 2.0, 4.0)
     cos_theta_max: float = math.cos(math.radians(30.0))
     stop_update_norm: float = 0.0
     min_inliers: int = 64
+    irls_delta: float = 0.0
 
     def _c(self):
         it = list(self.iters) + [0] * (4 - len(self.iters))
         dm = list(self.d_max) + [self.d_max[-1]] * (4 - len(self.d_max))
         return _IcpParams(self.levels, (ctypes.c_int32 * 4)(*it), (ctypes.c_double * 4)(*dm), self.cos_theta_max,
-                          self.stop_update_norm, self.min_inliers)
+                          self.stop_update_norm, self.min_inliers, self.irls_delta)
 
 
 @dataclass
@@ -251,16 +255,19 @@ def correspondences(sg, scan, kg, kf, T, d_max=0.5, cos_theta_max=math.cos(math.
     return res["kf_index"], res["inlier"]
 
 
-def normal_equations(sg, scan, kg, kf, T, d_max=0.5, cos_theta_max=math.cos(math.radians(30.0))):
+def normal_equations(sg, scan, kg, kf, T, d_max=0.5, cos_theta_max=math.cos(math.radians(30.0)), irls_delta=0.0):
+    """Normal equations at pose T; irls_delta > 0 weights each inlier by
+    1 / max(|r|, irls_delta) (the absolute-value objective's IRLS step)."""
     s = _f64(scan, (sg.rows, sg.cols, 4))
     k = _f64(kf, (kg.rows, kg.cols, 4))
     A = np.zeros(21)
     b = np.zeros(6)
     s2 = ctypes.c_double()
     ni, nv = ctypes.c_int64(), ctypes.c_int64()
-    _lib().orc_normal_equations(ctypes.byref(_geom(sg)), _ptr(s), ctypes.byref(_geom(kg)), _ptr(k),
-                                _ptr(pose12(T)), ctypes.c_double(d_max), ctypes.c_double(cos_theta_max), _ptr(A),
-                                _ptr(b), ctypes.byref(s2), ctypes.byref(ni), ctypes.byref(nv))
+    _lib().orc_normal_equations_irls(ctypes.byref(_geom(sg)), _ptr(s), ctypes.byref(_geom(kg)), _ptr(k),
+                                     _ptr(pose12(T)), ctypes.c_double(d_max), ctypes.c_double(cos_theta_max),
+                                     ctypes.c_double(irls_delta), _ptr(A), _ptr(b), ctypes.byref(s2),
+                                     ctypes.byref(ni), ctypes.byref(nv))
     return dict(A21=A, A=sym6(A), b=b, sum_r2=s2.value, inliers=ni.value, valid=nv.value)
 
 

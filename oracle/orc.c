@@ -293,11 +293,30 @@ int orc_residuals(const orc_geom *sg, const double *scan, const orc_geom *kg, co
     return 0;
 }
 
+/* IRLS weight of one residual for the absolute-value objective of           */
+/* Equation 1: w = 1 / max(|r|, delta), so that w r^2 = |r| away from zero;  */
+/* below delta the weight stays 1 / delta (the step then minimises Huber's   */
+/* function with threshold delta).  delta = 0 selects the squared objective */
+/* (w = 1).                                                                  */
+static double irls_weight(double r, double delta) {
+    if (delta <= 0.0) return 1.0;
+    double a = fabs(r);
+    return 1.0 / (a > delta ? a : delta);
+}
+
 /* Gauss-Newton normal equations of the squared Equation-1 residuals:         */
 /* A = sum J^T J (upper triangle, row-major, 21 entries), b = sum J^T r.      */
 int orc_normal_equations(const orc_geom *sg, const double *scan, const orc_geom *kg, const double *kf,
                          const double T[12], double d_max, double cos_theta_max, double A[21], double b[6],
                          double *sum_r2, int64_t *inliers, int64_t *valid) {
+    return orc_normal_equations_irls(sg, scan, kg, kf, T, d_max, cos_theta_max, 0.0, A, b, sum_r2, inliers, valid);
+}
+
+/* The same with each inlier's terms weighted by irls_weight(r, delta):       */
+/* A = sum w J^T J, b = sum w J^T r; sum_r2 stays the unweighted sum of r^2.  */
+int orc_normal_equations_irls(const orc_geom *sg, const double *scan, const orc_geom *kg, const double *kf,
+                              const double T[12], double d_max, double cos_theta_max, double delta, double A[21],
+                              double b[6], double *sum_r2, int64_t *inliers, int64_t *valid) {
     for (int k = 0; k < 21; k++) A[k] = 0.0;
     for (int k = 0; k < 6; k++) b[k] = 0.0;
     double s2 = 0.0;
@@ -310,10 +329,11 @@ int orc_normal_equations(const orc_geom *sg, const double *scan, const orc_geom 
             pair_at(sg, scan, kg, kf, T, d_max, cos_theta_max, i, j, &pr);
             if (!pr.inlier) continue;
             n_in++;
+            double w = irls_weight(pr.r, delta);
             int e = 0;
             for (int a = 0; a < 6; a++)
-                for (int c = a; c < 6; c++) A[e++] += pr.J[a] * pr.J[c];
-            for (int a = 0; a < 6; a++) b[a] += pr.J[a] * pr.r;
+                for (int c = a; c < 6; c++) A[e++] += w * pr.J[a] * pr.J[c];
+            for (int a = 0; a < 6; a++) b[a] += w * pr.J[a] * pr.r;
             s2 += pr.r * pr.r;
         }
     }
@@ -414,6 +434,9 @@ void orc_compose(const double A[12], const double B[12], double out[12]) {
 /* residuals of Equation 1 over re-associated projective correspondences,     */
 /* coarse-to-fine over a subsampled pyramid, followed by the registration     */
 /* quality of Section III-C (inliers over valid scan ranges) at level 0.      */
+/* With irls_delta > 0 every step is the reweighted step of the absolute-     */
+/* value objective (orc_normal_equations_irls); the quality terms stay        */
+/* unweighted and the returned JtJ, Jtr are the weighted ones.               */
 /* ------------------------------------------------------------------------ */
 
 int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, const double *kf,
@@ -436,7 +459,8 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
         for (int it = 0; it < p->iters[l]; it++) {
             double A[21], b[6], s2, xi[6], E[12];
             int64_t n_in, n_valid;
-            orc_normal_equations(&sl, sp, &kl, kp, T, p->d_max[l], p->cos_theta_max, A, b, &s2, &n_in, &n_valid);
+            orc_normal_equations_irls(&sl, sp, &kl, kp, T, p->d_max[l], p->cos_theta_max, p->irls_delta, A, b, &s2,
+                                      &n_in, &n_valid);
             if (n_in < p->min_inliers) {
                 status = ORC_NO_INLIERS;
                 stop = 1;
@@ -484,10 +508,11 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
             double r2 = pr.r * pr.r;
             s2 += r2;
             trunc += r2 < tau * tau ? r2 : tau * tau;
+            double w = irls_weight(pr.r, p->irls_delta);
             int e = 0;
             for (int a = 0; a < 6; a++)
-                for (int c = a; c < 6; c++) A[e++] += pr.J[a] * pr.J[c];
-            for (int a = 0; a < 6; a++) b[a] += pr.J[a] * pr.r;
+                for (int c = a; c < 6; c++) A[e++] += w * pr.J[a] * pr.J[c];
+            for (int a = 0; a < 6; a++) b[a] += w * pr.J[a] * pr.r;
         }
     }
     memcpy(res->T, T, sizeof(T));

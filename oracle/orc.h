@@ -44,6 +44,7 @@ typedef struct {
     double cos_theta_max;
     double stop_update_norm;
     int32_t min_inliers;
+    double irls_delta; /* 0: squared residuals; > 0: |r| by IRLS, weights 1 / max(|r|, irls_delta) */
 } orc_icp_params;
 
 typedef struct {
@@ -74,6 +75,9 @@ int orc_residuals(const orc_geom *sg, const double *scan, const orc_geom *kg, co
 int orc_normal_equations(const orc_geom *sg, const double *scan, const orc_geom *kg, const double *kf,
                          const double T[12], double d_max, double cos_theta_max, double A[21], double b[6],
                          double *sum_r2, int64_t *inliers, int64_t *valid);
+int orc_normal_equations_irls(const orc_geom *sg, const double *scan, const orc_geom *kg, const double *kf,
+                              const double T[12], double d_max, double cos_theta_max, double delta, double A[21],
+                              double b[6], double *sum_r2, int64_t *inliers, int64_t *valid);
 int orc_solve6(const double A[21], const double b[6], double xi[6]);
 void orc_exp_se3(const double xi[6], double T[12]);
 void orc_compose(const double A[12], const double B[12], double out[12]);

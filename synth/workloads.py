@@ -176,3 +176,25 @@ def config3(seed: int = 11, offset=(0.0, 0.0), rows: int = 128, cols: int = 2048
     FP64, so the rendered ranges do not depend on the offset beyond FP64
     rounding; T_world_kf carries it."""
     return config1(seed=seed, rows=rows, cols=cols, world_offset=offset, **kw)
+
+
+# ----------------------------------------------------------------------------
+# outlier patches: rectangles of a depth image moved along their rays
+# ----------------------------------------------------------------------------
+
+def outlier_patches(depth, seed: int, frac: float = 0.2, h: int = 8, w: int = 16, amp=(0.1, 0.3)):
+    """Copy of ``depth`` with about ``frac`` of its pixels in h x w rectangles
+    (seeded positions, overlaps allowed) whose returns are moved by one common
+    offset per rectangle, |offset| uniform in ``amp`` metres with a random
+    sign: surfaces that do not belong to the keyframe's scene (objects that
+    moved between the sweeps) but still pass a 0.5 m association gate."""
+    rng = np.random.Generator(np.random.PCG64(seed + 104729))
+    d = np.array(depth, copy=True)
+    rows, cols = d.shape
+    for _ in range(int(frac * rows * cols / (h * w))):
+        i = int(rng.integers(0, rows - h))
+        j = int(rng.integers(0, cols - w))
+        off = rng.uniform(*amp) * (1.0 if rng.random() < 0.5 else -1.0)
+        blk = d[i:i + h, j:j + w]
+        d[i:i + h, j:j + w] = np.where(blk > 0, blk + off, blk)
+    return d
