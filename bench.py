@@ -50,9 +50,10 @@ HBM_PEAK_GBS = 8000.0
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
-TRAFFIC_KIB = {"single": (2519.21, 64.17), "batch": (498164.42, 983.0)}
-TRAFFIC_SRC_HASH = "404e3fe92569c436"
-TRAFFIC_SRC = ("ups_icp.hip", "ups_icp.hpp", "ups_device.hpp", "ups_internal.hpp")
+TRAFFIC_KIB = {"single": (2519.17, 64.17), "batch": (498219.22, 983.0)}
+TRAFFIC_SRC_HASH = "0ca3551e6c84c740"
+TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip", "ups_icp.hpp",
+               "ups_device.hpp", "ups_internal.hpp")
 
 
 def traffic_bytes(which):
@@ -368,9 +369,45 @@ def run_batch(args, torch, ups, synth, W, stream):
     }
     if not args.no_proposal:
         out["learned"] = run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms, res)
+    if args.precision == "kahan":
+        out["irls"] = run_irls(args, torch, ups, synth, ctx, items, pairs, stream, ms_register, launch_us, errs)
     batch.close()
     ctx.close()
     return out
+
+
+def run_irls(args, torch, ups, synth, ctx, items, pairs, stream, ms_register, launch_us, errs_sq):
+    """The same batch under the absolute-value objective of Equation 1 (IRLS,
+    delta = the 1 cm range noise): registration time, level-0 launch time and
+    pose errors next to the squared objective's."""
+    dev = torch.device("cuda:0")
+    delta = 0.01
+    params = ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6, irls_delta=delta)
+    b = ups.Batch(ctx, items, params)
+    init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
+    results = torch.zeros((N_BATCH, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
+    b.register(init, results)
+    torch.cuda.synchronize()
+    res = ups.read_results(results)
+    ms = time_graph(torch, capture(torch, stream, lambda: b.register(init, results)), stream, args.batch_steps)
+    with torch.cuda.stream(stream):
+        b.time_iteration(0, 5 if args.profile_run else 30)
+        us = b.time_iteration(0, 5 if args.profile_run else 50)
+    b.close()
+    e = np.array([synth.pose_error(r["T"], p["T_gt"]) for r, p in zip(res, pairs)])
+    px_it = sum(sum(r["level_iters"][l] * (p["geom"].rows >> l) * (p["geom"].cols >> l) for l in range(LEVELS))
+                for r, p in zip(res, pairs))
+    log(f"IRLS (delta {delta} m): register {ms:.3f} ms (squared {ms_register:.3f} ms), level-0 launch "
+        f"{us:.1f} us (squared {launch_us:.1f} us), median error {np.median(e[:, 0]):.2e} rad "
+        f"{np.median(e[:, 1]):.2e} m")
+    return {"objective": f"absolute residuals of Equation 1 by IRLS, weights 1/max(|r|, {delta} m)",
+            "ms_register": round(ms, 4), "ms_register_squared": round(ms_register, 4),
+            "level0_launch_us": round(us, 2), "level0_launch_us_squared": round(launch_us, 2),
+            "pixel_iterations_executed": int(px_it),
+            "pose_error_vs_truth_median_rad_m": [float(np.median(e[:, 0])), float(np.median(e[:, 1]))],
+            "pose_error_vs_truth_median_rad_m_squared": [float(np.median(errs_sq[:, 0])),
+                                                         float(np.median(errs_sq[:, 1]))],
+            "status_counts": {ups.STATUS[st]: int(sum(r["status"] == st for r in res)) for st in ups.STATUS}}
 
 
 def _successes(res, pairs, synth):

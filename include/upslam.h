@@ -101,7 +101,12 @@ typedef struct {
 
 /* Registration (Section III-B).  Coarse-to-fine over `levels` (1..4) pyramid
  * levels (level l keeps every 2^l-th row and column); iters[l] Gauss-Newton
- * steps at level l on the squared point-to-plane residuals of Equation 1.
+ * steps at level l on the squared point-to-plane residuals of Equation 1, or,
+ * with irls_delta > 0, on Equation 1's absolute residuals by iteratively
+ * reweighted least squares: each inlier's terms carry the weight
+ * 1 / max(|r|, irls_delta) (the fixed point minimises Huber's function with
+ * that threshold, |r| - irls_delta/2 above it).  irls_delta = 0: squared
+ * objective, bit-identical to the unweighted path.
  * Omega: inlier iff both surfels are valid, |q - s1| <= d_max[l] and
  * (R n2).n1 >= cos_theta_max.  A level ends early when stop_update_norm > 0 and
  * the step norm |xi| falls below it.  min_inliers: fewer correspondences stop
@@ -115,13 +120,15 @@ typedef struct {
     double stop_update_norm;
     int32_t min_inliers;
     int32_t precision; /* UPS_PREC_* */
+    float irls_delta;  /* 0: squared residuals; >= 1e-6: absolute residuals by IRLS (metres) */
 } ups_icp_params;
 
 /* Result of a registration (device memory).  T: final pose.  The quality block
  * is evaluated at level 0 and the final pose (Section III-C): inliers over
  * valid scan ranges, rms of inlier residuals, truncated cost sum over valid
  * scan pixels of min(r^2, d_max[0]^2) with non-inliers counting d_max[0]^2, and
- * the normal equations (upper triangle of J^T J row-major, J^T r) there. */
+ * the normal equations (upper triangle of J^T J row-major, J^T r) there, with
+ * the IRLS weights when irls_delta > 0 (the quality terms are unweighted). */
 typedef struct {
     ups_pose T;
     double rms, trunc_cost, inlier_ratio;
@@ -300,8 +307,8 @@ ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_in
 ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result *results_d, void *stream);
 
 /* Loop-closure grid search (Section III-C): for every registration k of the
- * batch, score the candidate transforms base_d[k] * G_c by a low-resolution
- * projective alignment check -- the number of Omega inliers (thresholds
+ * batch, score the candidate transforms base_d[k] * G_c by a coarse projective
+ * alignment test -- the number of Omega inliers (thresholds
  * d_max, cos_theta_max) of the scan's pyramid level `level` against the
  * keyframe's -- and write the best candidate (most inliers, the lowest c among
  * equals) to best_d[k] and its score to best_score_d[k] (may be NULL).

@@ -57,7 +57,7 @@ class ups_normal_params(ctypes.Structure):
 class ups_icp_params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * 4), ("d_max", ctypes.c_float * 4),
                 ("cos_theta_max", ctypes.c_float), ("stop_update_norm", ctypes.c_double),
-                ("min_inliers", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("min_inliers", ctypes.c_int32), ("precision", ctypes.c_int32), ("irls_delta", ctypes.c_float)]
 
 
 class ups_icp_result(ctypes.Structure):
@@ -185,12 +185,14 @@ class IcpParams:
     stop_update_norm: float = 0.0
     min_inliers: int = 64
     precision: int = PREC_KAHAN_F64
+    irls_delta: float = 0.0  # > 0: absolute residuals (Equation 1) by IRLS, weights 1 / max(|r|, irls_delta)
 
     def c(self):
         it = list(self.iters) + [0] * (4 - len(self.iters))
         dm = list(self.d_max) + [self.d_max[-1]] * (4 - len(self.d_max))
         return ups_icp_params(self.levels, (ctypes.c_int32 * 4)(*it), (ctypes.c_float * 4)(*dm),
-                              self.cos_theta_max, self.stop_update_norm, self.min_inliers, self.precision)
+                              self.cos_theta_max, self.stop_update_norm, self.min_inliers, self.precision,
+                              self.irls_delta)
 
 
 @dataclass

@@ -213,6 +213,10 @@ static ups_status check_icp_params(const ups_icp_params *p) {
     UPS_REQUIRE(p->cos_theta_max >= -1.f && p->cos_theta_max <= 1.f, "cos_theta_max must be in [-1, 1]");
     UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
     UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
+    UPS_REQUIRE(p->irls_delta == 0.f || (p->irls_delta >= 1e-6f && std::isfinite(p->irls_delta)),
+                "irls_delta must be 0 or a finite value >= 1e-6");
+    UPS_REQUIRE(p->irls_delta == 0.f || p->precision == UPS_PREC_KAHAN_F64,
+                "the IRLS objective (irls_delta > 0) needs precision UPS_PREC_KAHAN_F64");
     return UPS_OK;
 }
 
@@ -294,6 +298,7 @@ ups_status ups_register_scan_world(ups_context *ctx, const ups_geom *scan_g, con
                                    void *stream) {
     ups_status st;
     if ((st = check_world_pose(world_kf_h)) != UPS_OK) return st;
+    UPS_REQUIRE(p == nullptr || p->irls_delta == 0.f, "the world-frame variant has no IRLS objective");
     return register_impl(ctx, scan_g, scan_surfel_d, kf_g, kf_surfel_d, world_kf_h, init_d, p, result_d, stream);
 }
 

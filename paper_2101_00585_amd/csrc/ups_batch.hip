@@ -297,6 +297,7 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
     a.prev_level = -1;
     a.d_max2 = b->p.d_max[level] * b->p.d_max[level];
     a.cos_theta = b->p.cos_theta_max;
+    a.irls_delta = b->p.irls_delta;
     a.min_inliers = b->p.min_inliers;
     ups_status st;
     if ((st = launch_activate_batch(b->d_inst, b->n, s)) != UPS_OK) return st;
@@ -354,6 +355,7 @@ ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.cos_theta = p.cos_theta_max;
+    a.irls_delta = p.irls_delta;
     a.min_inliers = p.min_inliers;
     a.stop_norm = p.stop_update_norm;
     a.prev_level = -1;

@@ -1,6 +1,6 @@
-// Loop-closure grid search (UPSLAM Section III-C): several hundred candidate
-// transforms of every registration of a batch are scored by a low-resolution
-// projective alignment check -- the number of Omega inliers at a coarse
+// Loop-closure grid search (UPSLAM Section III-C): a few hundred candidate
+// transforms of every registration of a batch are compared by a coarse
+// projective alignment test -- the number of Omega inliers at a subsampled
 // pyramid level -- and the best candidate becomes the start of the
 // full-resolution registration.
 //

@@ -24,643 +24,9 @@
 // The same kernels serve one registration (descriptor passed by value) and a
 // batch of registrations of different sizes (descriptors in device memory,
 // block -> (registration, tile) through a per-level prefix table).
-#include "ups_icp.hpp"
+#include "ups_icp_kernels.hpp"
 
 namespace ups {
-
-// ---------------------------------------------------------------- reductions
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-    int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-    int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over each 16-lane row (quad xor 1, quad xor 2, half-row mirror, row
-// mirror); every lane of a row ends with the bitwise-same row sum.
-template <typename T>
-__device__ __forceinline__ T row_sum(T v) {
-    if constexpr (sizeof(T) == 8) {
-        v += dpp_d<0xB1>(v);
-        v += dpp_d<0x4E>(v);
-        v += dpp_d<0x141>(v);
-        v += dpp_d<0x140>(v);
-    } else {
-        v += dpp_f<0xB1>(v);
-        v += dpp_f<0x4E>(v);
-        v += dpp_f<0x141>(v);
-        v += dpp_f<0x140>(v);
-    }
-    return v;
-}
-
-__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-// Per-thread accumulation of the per-pixel terms in the three precision modes.
-template <int PREC, int NV>
-struct ThreadAcc;
-
-// Compensated FP32 where it pays: the Gauss-Newton fixed point is where
-// J^T r vanishes, so J^T r (values 21..26), sum r^2 (27) and the truncated
-// cost (30) are Kahan-compensated; the 21 J^T J entries, whose rounding only
-// perturbs the step size, are plain FP32 sums; counts are exact.  The
-// compensated values are summed plainly over a group of up to 4 pixels and
-// each group sum enters the Kahan sum (flush), which keeps the compensation
-// at a quarter of the per-pixel cost; a 4-term FP32 sum adds at most 3 ulp
-// of its terms' magnitude before compensation.
-template <int NV>
-struct ThreadAcc<UPS_PREC_KAHAN_F64, NV> {
-    static constexpr int NC = NV > 30 ? 8 : 7;  // compensated values
-    float s[NV], c[NC], g[NC];
-    static __device__ __forceinline__ constexpr int comp(int v) { return (v >= 21 && v < 28) ? v - 21 : (v == 30 ? 7 : -1); }
-    static __device__ __forceinline__ constexpr int value_of(int j) { return j < 7 ? 21 + j : 30; }
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int v = 0; v < NV; v++) s[v] = 0.f;
-#pragma unroll
-        for (int j = 0; j < NC; j++) c[j] = g[j] = 0.f;
-    }
-    __device__ __forceinline__ void add(int v, float x) {
-        if (comp(v) >= 0) g[comp(v)] += x;
-        else s[v] += x;
-    }
-    __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
-    // the group sums enter the compensated sums
-    __device__ __forceinline__ void flush() {
-#pragma unroll
-        for (int j = 0; j < NC; j++) {
-            kahan_add(s[value_of(j)], c[j], g[j]);
-            g[j] = 0.f;
-        }
-    }
-    __device__ __forceinline__ double get(int v) const {
-        return comp(v) >= 0 ? (double)s[v] - (double)c[comp(v)] : (double)s[v];
-    }
-};
-
-template <int NV>
-struct ThreadAcc<UPS_PREC_F32, NV> {  // plain FP32
-    float s[NV];
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int v = 0; v < NV; v++) s[v] = 0.f;
-    }
-    __device__ __forceinline__ void add(int v, float x) { s[v] += x; }
-    __device__ __forceinline__ void count(int v) { s[v] += 1.f; }
-    __device__ __forceinline__ void flush() {}
-    __device__ __forceinline__ float get(int v) const { return s[v]; }
-};
-
-template <int NV>
-struct ThreadAcc<UPS_PREC_F64, NV> {  // FP64 (callers add exact FP64 products)
-    double s[NV];
-    __device__ __forceinline__ void zero() {
-#pragma unroll
-        for (int v = 0; v < NV; v++) s[v] = 0.0;
-    }
-    __device__ __forceinline__ void add(int v, double x) { s[v] += x; }
-    __device__ __forceinline__ void fma(int v, double a, double b) { s[v] = ::fma(a, b, s[v]); }
-    __device__ __forceinline__ void count(int v) { s[v] += 1.0; }
-    __device__ __forceinline__ void flush() {}
-    __device__ __forceinline__ double get(int v) const { return s[v]; }
-};
-
-template <int PREC>
-using AccOf = typename std::conditional<PREC == UPS_PREC_F32, float, double>::type;
-
-// Add one inlier's 28 terms: the upper triangle of J^T J, J^T r and r^2.
-template <int PREC, int NV>
-__device__ __forceinline__ void add_terms(ThreadAcc<PREC, NV> &acc, const Pair &pr) {
-    const float3 qn = cross3(pr.q, pr.n1);
-    if constexpr (PREC == UPS_PREC_F64) {
-        const double J[6] = {qn.x, qn.y, qn.z, pr.n1.x, pr.n1.y, pr.n1.z};
-        const double r = pr.r;
-        int e = 0;
-#pragma unroll
-        for (int u = 0; u < 6; u++)
-#pragma unroll
-            for (int w = u; w < 6; w++) acc.fma(e++, J[u], J[w]);
-#pragma unroll
-        for (int u = 0; u < 6; u++) acc.fma(21 + u, J[u], r);
-        acc.fma(27, r, r);
-    } else {
-        const float J[6] = {qn.x, qn.y, qn.z, pr.n1.x, pr.n1.y, pr.n1.z};
-        int e = 0;
-#pragma unroll
-        for (int u = 0; u < 6; u++)
-#pragma unroll
-            for (int w = u; w < 6; w++) acc.add(e++, J[u] * J[w]);
-#pragma unroll
-        for (int u = 0; u < 6; u++) acc.add(21 + u, J[u] * pr.r);
-        acc.add(27, pr.r * pr.r);
-    }
-    acc.count(28);
-}
-
-// Sum NV per-thread values over the 256-thread block in a fixed order: DPP row
-// sums, then the 16 row sums of each value added in row order.  tot[v] holds
-// the block total of value v for every thread after the call.
-template <int NV, typename Acc>
-__device__ __forceinline__ void block_reduce(Acc (&x)[NV], Acc (*rows)[16], Acc *tot) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int v = 0; v < NV; v++) {
-        const Acc y = row_sum<Acc>(x[v]);
-        if ((lane & 15) == 0) rows[v][wave * 4 + (lane >> 4)] = y;
-    }
-    __syncthreads();
-    if (tid < NV) {
-        Acc t = 0;
-#pragma unroll
-        for (int r = 0; r < 16; r++) t += rows[tid][r];
-        tot[tid] = t;
-    }
-    __syncthreads();
-}
-
-// Load this thread's share of `n` block partials (partials t, t+256, ... for
-// thread t) and add them up in that fixed order; block_reduce finishes.
-template <int NV, typename Acc>
-__device__ __forceinline__ void load_partials(const double *part, int n, Acc (&x)[NV]) {
-#pragma unroll
-    for (int v = 0; v < NV; v++) x[v] = 0;
-    for (int b = threadIdx.x; b < n; b += kBlock) {
-        const double *pb = part + (size_t)b * kPartialStride;
-#pragma unroll
-        for (int v = 0; v < NV; v++) x[v] += (Acc)pb[v];
-    }
-}
-
-template <int NV, typename Acc>
-__device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (*rows)[16], Acc *tot) {
-    Acc x[NV];
-    load_partials<NV, Acc>(part, n, x);
-    block_reduce<NV, Acc>(x, rows, tot);
-}
-
-// --------------------------------------------------------- FP64 / FP32 solve
-
-template <typename T>
-__device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
-    T A[6][6], L[6][6], inv[6];
-    int e = 0;
-    for (int a = 0; a < 6; a++)
-        for (int c = a; c < 6; c++) {
-            A[a][c] = A21[e];
-            A[c][a] = A21[e];
-            e++;
-        }
-    T maxd = 0;
-    for (int a = 0; a < 6; a++) maxd = A[a][a] > maxd ? A[a][a] : maxd;
-    if (!(maxd > T(0))) return UPS_DEGENERATE;
-    for (int c = 0; c < 6; c++) {
-        T d = A[c][c];
-        for (int k = 0; k < c; k++) d -= L[c][k] * L[c][k];
-        if (!(d > T(1e-12) * maxd)) return UPS_DEGENERATE;
-        L[c][c] = sqrt(d);
-        inv[c] = T(1) / L[c][c];
-        for (int r = c + 1; r < 6; r++) {
-            T s = A[r][c];
-            for (int k = 0; k < c; k++) s -= L[r][k] * L[c][k];
-            L[r][c] = s * inv[c];
-        }
-    }
-    T y[6];
-    for (int r = 0; r < 6; r++) {
-        T s = -b[r];
-        for (int k = 0; k < r; k++) s -= L[r][k] * y[k];
-        y[r] = s * inv[r];
-    }
-    for (int r = 5; r >= 0; r--) {
-        T s = y[r];
-        for (int k = r + 1; k < 6; k++) s -= L[k][r] * xi[k];
-        xi[r] = s * inv[r];
-    }
-    return UPS_CONVERGED;
-}
-
-// R, t <- Exp(xi) (R, t) with xi = (omega, v): Rodrigues rotation and the V
-// matrix.  Below |omega| = 1/4 the three coefficients sin(th)/th,
-// (1-cos th)/th^2 and (th-sin th)/th^3 come from their Taylor series to the
-// th^14 term (remainder < 1e-20), which avoids the cancellation of the closed
-// forms and any sin/cos; above it the closed forms are used.
-template <typename T>
-__device__ void exp_compose(const T *xi, double *R, double *t) {
-    const T w0 = xi[0], w1 = xi[1], w2 = xi[2];
-    const T th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
-    T A, B, C;
-    if (th < T(0.25)) {
-        // 1/n! for n = 1..17
-        constexpr double f[18] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040,
-                                  1.0 / 40320, 1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600,
-                                  1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0,
-                                  1.0 / 20922789888000.0, 1.0 / 355687428096000.0};
-        A = B = C = 0;
-        for (int k = 7; k >= 0; k--) {
-            const T sg = (k & 1) ? T(-1) : T(1);
-            A = A * th2 + sg * (T)f[2 * k + 1];
-            B = B * th2 + sg * (T)f[2 * k + 2];
-            C = C * th2 + sg * (T)f[2 * k + 3];
-        }
-    } else {
-        A = sin(th) / th;
-        B = (T(1) - cos(th)) / th2;
-        C = (th - sin(th)) / (th2 * th);
-    }
-    const T K[3][3] = {{0, -w2, w1}, {w2, 0, -w0}, {-w1, w0, 0}};
-    T K2[3][3], E[3][3], V[3][3];
-    for (int a = 0; a < 3; a++)
-        for (int c = 0; c < 3; c++) K2[a][c] = K[a][0] * K[0][c] + K[a][1] * K[1][c] + K[a][2] * K[2][c];
-    for (int a = 0; a < 3; a++)
-        for (int c = 0; c < 3; c++) {
-            const T I = (a == c) ? T(1) : T(0);
-            E[a][c] = I + A * K[a][c] + B * K2[a][c];
-            V[a][c] = I + B * K[a][c] + C * K2[a][c];
-        }
-    T te[3], Ro[9], to[3];
-    for (int a = 0; a < 3; a++) te[a] = V[a][0] * xi[3] + V[a][1] * xi[4] + V[a][2] * xi[5];
-    for (int k = 0; k < 9; k++) Ro[k] = (T)R[k];
-    for (int k = 0; k < 3; k++) to[k] = (T)t[k];
-    for (int a = 0; a < 3; a++) {
-        for (int c = 0; c < 3; c++)
-            R[3 * a + c] = (double)(E[a][0] * Ro[c] + E[a][1] * Ro[3 + c] + E[a][2] * Ro[6 + c]);
-        t[a] = (double)(E[a][0] * to[0] + E[a][1] * to[1] + E[a][2] * to[2] + te[a]);
-    }
-}
-
-// Gauss-Newton step from the reduced totals (thread 0).  Updates the state in
-// place: pose, iteration count, step norm, convergence of the level, or the
-// failure status that stops the registration with the pose unchanged.
-template <typename T>
-__device__ void gn_step(const StepArgs &a, const T *tot, RegState &S) {
-    const double n_in = (double)tot[28];
-    T xi[6];
-    const int st = (n_in < (double)a.min_inliers) ? UPS_NO_INLIERS : cholesky_solve6<T>(tot, tot + 21, xi);
-    if (st != UPS_CONVERGED) {
-        S.status = st;
-        S.stop = 1;
-        return;
-    }
-    exp_compose<T>(xi, S.R, S.t);
-    S.iters_run += 1;
-    S.level_iters[a.prev_level] += 1;
-    T nrm = 0;
-    for (int k = 0; k < 6; k++) nrm += xi[k] * xi[k];
-    S.last_norm = (double)sqrt(nrm);
-    if (a.stop_norm > 0.0 && S.last_norm < a.stop_norm) S.level_active = 0;
-}
-
-// ------------------------------------------------------------------ kernel
-
-// Partials a launch over `nblocks` blocks leaves for its successor: one per
-// block, or a single folded one when there are more than 256.
-__device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
-
-// FUSED: the block first applies the previous launch's update itself (step 0
-// above; single registrations).  Otherwise (batches) a separate one-block-per-
-// registration launch has already applied it and left the pose, and whether
-// this launch has work for the registration, in state slot 0.
-// WORLD: the world-frame variant (state pose = the scan's world pose).
-template <int K, int PREC, int MODE, bool FUSED, bool WORLD = false>
-__device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
-    constexpr int NV = (MODE == MODE_ITER) ? 29 : 31;  // EVAL adds valid count and truncated cost
-    using Acc = AccOf<PREC>;
-    const int tid = threadIdx.x;
-    const int l = a.level;
-    const int ntiles = I.nblocks[l];
-    RegState *slot_in = I.state + (FUSED ? a.parity : 0), *slot_out = I.state + (a.parity ^ 1);
-    const double *part_in = I.partials + (size_t)a.parity * I.pstride * kPartialStride;
-    double *part_out = I.partials + (size_t)(FUSED ? (a.parity ^ 1) : 0) * I.pstride * kPartialStride;
-
-    __shared__ RegState S;
-    __shared__ Acc rows[31][16];
-    __shared__ Acc tot[32];
-    __shared__ int active;
-    const DGeom sg = I.sg[l], kg = I.kg[l];
-    const float4 *__restrict__ scan = I.scan[l];
-    const float4 *__restrict__ kf = I.kf[l];
-    const int npix = sg.rows * sg.cols;
-    const int base = tile * (kBlock * K);
-
-    // ---- issue the independent loads together: the first scan surfel and
-    // its ray-table column, the previous launch's block partials and the state.
-    // Scan loads are clamped into the image (the last wavefronts of a tile may
-    // run past it) and masked afterwards, so no load sits behind a branch.
-    const int pw0 = __builtin_amdgcn_readfirstlane(base + (tid & ~63));
-    // column of this thread's pixel; it advances by kBlock mod cols per pixel
-    const int col_step = kBlock % sg.cols;
-    int jn = (base + tid) % sg.cols;
-    float4 nxt = ldg_u(scan, (uint32_t)min(base + tid, npix - 1));
-    float2 nxt_a = ldg_u(sg.lut_col, (uint32_t)jn << sg.lshift);
-    if (!FUSED) {
-        if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
-        if (MODE == MODE_EVAL && slot_in->skip) return;
-        if (tid == 0) S = *slot_in;
-        __syncthreads();
-    } else {
-        Acc px[29];
-        load_partials<29, Acc>(part_in, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0, px);
-        if (tid == 0) S = *slot_in;
-        __syncthreads();
-        // ---- 0. the previous launch's update, solved identically by every block
-        if (S.pending && !S.stop) {
-            block_reduce<29, Acc>(px, rows, tot);
-            if (tid == 0) gn_step<Acc>(a, tot, S);
-        }
-        if (tid == 0) {
-            S.pending = 0;
-            if (MODE == MODE_ITER && a.first_of_level) S.level_active = 1;
-            if (MODE == MODE_EVAL && a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
-            active = (MODE == MODE_EVAL) || (!S.stop && S.level_active);
-        }
-        __syncthreads();
-        if (!active) {
-            if (tile == 0 && tid == 0) *slot_out = S;
-            return;
-        }
-    }
-
-    // ---- 1. association of K pixels per thread at the updated pose (the pose
-    // is block-uniform: kept in scalar registers)
-    Rt32 T;
-#pragma unroll
-    for (int k = 0; k < 9; k++) T.r[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.R[k])));
-#pragma unroll
-    for (int k = 0; k < 3; k++) T.t[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int((float)S.t[k])));
-    Rt32 Wk;
-    if constexpr (WORLD) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) Wk.r[k] = (float)I.wR[k];
-#pragma unroll
-        for (int k = 0; k < 3; k++) Wk.t[k] = (float)I.wt[k];
-    }
-    ThreadAcc<PREC, NV> acc;
-    acc.zero();
-    // pixels in pairs: both pixels' keyframe gathers are in flight before the
-    // first of them is consumed, and the next pair's scan loads behind them
-    constexpr int P = (K >= 2) ? 2 : 1;
-    float4 nx[P];
-    float2 na[P];
-    int jc[P];
-    nx[0] = nxt;
-    na[0] = nxt_a;
-    jc[0] = jn;
-#pragma unroll
-    for (int u = 1; u < P; u++) {
-        jc[u] = jc[u - 1] + col_step;
-        jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-        nx[u] = ldg_u(scan, (uint32_t)min(base + u * kBlock + tid, npix - 1));
-        na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
-    }
-    int pw = pw0;
-    // groups of up to 4 pixels (the Kahan group), two unrolled per trip so
-    // that the compensated sums need no register copies between trips
-    constexpr int GP = K < 4 ? K : 4;
-    bool done = false;
-#pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += GP) {
-#pragma unroll
-        for (int k = k0; k < k0 + GP; k += P) {
-            if (pw >= npix) {
-                done = true;
-                break;
-            }
-            Gather G[P];
-            float sw[P];
-#pragma unroll
-            for (int u = 0; u < P; u++) {
-                const float4 s2 = make_float4(nx[u].x, nx[u].y, nx[u].z,
-                                              (base + (k + u) * kBlock + tid < npix) ? nx[u].w : 0.f);
-                sw[u] = s2.w;
-                const int i = min(pw + u * kBlock, npix - 1) / sg.cols;
-                const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
-                if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk);
-                else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T);
-                // keep the consumers of these gathers below the next pixel's scan side
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            {
-                const bool more = k + P < K;
-#pragma unroll
-                for (int u = 0; u < P; u++) {
-                    jc[u] += more ? P * col_step : 0;
-                    jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-                    jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-                    nx[u] = ldg_u(scan, (uint32_t)min(base + (more ? k + P + u : k + u) * kBlock + tid, npix - 1));
-                    na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int u = 0; u < P; u++) {
-                bool inl;
-                float r;
-                float3 n1;
-                if constexpr (WORLD) kf_side_world(kg, G[u], Wk, a.d_max2, a.cos_theta, inl, r, n1);
-                else kf_side(kg, G[u], a.d_max2, a.cos_theta, inl, r, n1);
-                if (inl) {
-                    Pair pr;
-                    pr.inlier = true;
-                    pr.r = r;
-                    pr.q = G[u].q;
-                    pr.n1 = n1;
-                    add_terms<PREC, NV>(acc, pr);
-                }
-                if (MODE == MODE_EVAL) {
-                    if (range_ok(sg, sw[u])) {
-                        acc.count(29);
-                        acc.add(30, inl ? fminf(r * r, a.tau2) : a.tau2);
-                    }
-                }
-            }
-            pw = __builtin_amdgcn_readfirstlane(pw + P * kBlock);
-        }
-        acc.flush();
-        if (done) break;
-    }
-
-    // ---- 2. block partial
-    {
-        Acc x[NV];
-#pragma unroll
-        for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
-        block_reduce<NV, Acc>(x, rows, tot);
-    }
-    if (tid < NV) part_out[(size_t)tile * kPartialStride + tid] = (double)tot[tid];
-    if (FUSED && tile == 0 && tid == 0) {
-        S.pending = (MODE == MODE_ITER);
-        S.npartials = ntiles;
-        *slot_out = S;
-    }
-}
-
-template <int K, int PREC, int MODE, bool WORLD>
-__global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
-    icp_block<K, PREC, MODE, true, WORLD>(I, a, blockIdx.x);
-}
-
-// Batch: block -> (registration, tile) by binary search in the level's prefix
-// table of tile counts (tile_start[n] = total blocks).
-template <int K, int PREC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
-                                                      const int *__restrict__ tile_start, int n, StepArgs a) {
-    const int b = blockIdx.x;
-    int lo = 0, hi = n;  // the last k with tile_start[k] <= b
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tile_start[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    icp_block<K, PREC, MODE, false>(insts[lo], a, b - tile_start[lo]);
-}
-
-// A subset of the batch (a Compact list): a fixed grid strides over the
-// subset's tiles, so the launch costs little when the subset is small.
-template <int K, int PREC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restrict__ insts,
-                                                           const Compact *__restrict__ hdr,
-                                                           const int *__restrict__ list,
-                                                           const int *__restrict__ start, StepArgs a) {
-    const int cnt = hdr->count, total = hdr->total[a.level];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        int lo = 0, hi = cnt;  // the last m with start[m] <= t
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (start[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-        icp_block<K, PREC, MODE, false>(insts[list[lo]], a, t - start[lo]);
-    }
-}
-
-// Batch, between two Gauss-Newton launches: one block per registration
-// reduces the partials of the launch that just ran (if it processed the
-// registration), applies the update, and decides whether the next launch
-// processes the registration.  a.prev_level: level of that launch;
-// a.first_of_level: the next launch starts a new level; a.check_max_iters: it
-// was the last launch of level 0.
-template <int PREC>
-__device__ __forceinline__ void solve_block(const Inst &I, const StepArgs &a) {
-    using Acc = AccOf<PREC>;
-    __shared__ RegState S;
-    __shared__ Acc rows[29][16];
-    __shared__ Acc tot[32];
-    if (threadIdx.x == 0) S = I.state[0];
-    __syncthreads();
-    if (S.active && !S.stop) {
-        reduce_partials<29, Acc>(I.partials, npartials_of(I.nblocks[a.prev_level]), rows, tot);
-        if (threadIdx.x == 0) gn_step<Acc>(a, tot, S);
-    }
-    if (threadIdx.x == 0) {
-        if (a.first_of_level) S.level_active = 1;
-        if (a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
-        S.active = !S.stop && S.level_active;
-        I.state[0] = S;
-    }
-    __syncthreads();  // S is reused when the caller loops
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_solve_batch(const Inst *__restrict__ insts, StepArgs a) {
-    solve_block<PREC>(insts[blockIdx.x], a);
-}
-
-// The registrations of a Compact list only, a small grid striding over them.
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_solve_batch_list(const Inst *__restrict__ insts,
-                                                             const Compact *__restrict__ hdr,
-                                                             const int *__restrict__ list, StepArgs a) {
-    const int cnt = hdr->count;
-    for (int m = blockIdx.x; m < cnt; m += gridDim.x) solve_block<PREC>(insts[list[m]], a);
-}
-
-// One block: the evaluation partials -> result (quality at the final pose,
-// plus the state's pose, status, iteration count and last step norm), or ->
-// normal equations.
-template <int PREC>
-__device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_result *res, ups_normal_eq *neq) {
-    using Acc = AccOf<PREC>;
-    __shared__ Acc rows[31][16];
-    __shared__ Acc tot[32];
-    const RegState *S = I.state + parity;
-    if (S->skip) return;  // masked out of this batch call: the result is left as it was
-    reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, npartials_of(I.nblocks[0]),
-                             rows, tot);
-    if (threadIdx.x != 0) return;
-    const double n_in = (double)tot[28], n_valid = (double)tot[29];
-    if (res) {
-        ups_icp_result *r = res;
-        if (I.world) {
-            // scan -> keyframe = (keyframe world pose)^-1 (scan world pose), FP64
-            for (int a = 0; a < 3; a++) {
-                for (int c = 0; c < 3; c++)
-                    r->T.R[3 * a + c] = I.wR[a] * S->R[c] + I.wR[3 + a] * S->R[3 + c] + I.wR[6 + a] * S->R[6 + c];
-                r->T.t[a] = I.wR[a] * (S->t[0] - I.wt[0]) + I.wR[3 + a] * (S->t[1] - I.wt[1]) +
-                            I.wR[6 + a] * (S->t[2] - I.wt[2]);
-            }
-        } else {
-            for (int k = 0; k < 9; k++) r->T.R[k] = S->R[k];
-            for (int k = 0; k < 3; k++) r->T.t[k] = S->t[k];
-        }
-        r->status = S->status;
-        r->iters_run = S->iters_run;
-        for (int k = 0; k < 4; k++) r->level_iters[k] = S->level_iters[k];
-        r->last_update_norm = S->last_norm;
-        for (int k = 0; k < 21; k++) r->JtJ[k] = (double)tot[k];
-        for (int k = 0; k < 6; k++) r->Jtr[k] = (double)tot[21 + k];
-        r->inliers = (int64_t)n_in;
-        r->valid = (int64_t)n_valid;
-        r->inlier_ratio = n_valid > 0 ? n_in / n_valid : 0.0;
-        r->rms = n_in > 0 ? sqrt((double)tot[27] / n_in) : 0.0;
-        r->trunc_cost = (double)tot[30];
-    }
-    if (neq) {
-        ups_normal_eq *q = neq;
-        for (int k = 0; k < 21; k++) q->JtJ[k] = (double)tot[k];
-        for (int k = 0; k < 6; k++) q->Jtr[k] = (double)tot[21 + k];
-        q->sum_r2 = (double)tot[27];
-        q->inliers = (int64_t)n_in;
-        q->valid = (int64_t)n_valid;
-    }
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_finish_one(Inst I, int parity) {
-    finish_block<PREC>(I, parity, I.res, I.neq);
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict__ insts, int parity,
-                                                         ups_icp_result *results) {
-    finish_block<PREC>(insts[blockIdx.x], parity, results + blockIdx.x, nullptr);
-}
-
-// More than 256 partials: fold them into one before the next launch reads
-// them (keeps the per-block read of step 0 bounded).
-template <int PREC, int NV>
-__global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
-    using Acc = AccOf<PREC>;
-    __shared__ Acc rows[NV][16];
-    __shared__ Acc tot[32];
-    RegState *S = I.state + parity;
-    double *part = I.partials + (size_t)parity * I.pstride * kPartialStride;
-    if (NV == 29 && !S->pending) return;
-    reduce_partials<NV, Acc>(part, S->npartials, rows, tot);
-    if (threadIdx.x < NV) part[threadIdx.x] = (double)tot[threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x == 0) S->npartials = 1;
-}
 
 // ------------------------------------------------- pyramid + registration init
 
@@ -875,95 +241,6 @@ int pick_k_single(int npix) {
     return K;
 }
 
-// Compile-time dispatch of (pixels per thread, precision, mode).
-#define UPS_CASE_K(KV, ...)         \
-    case KV: {                      \
-        constexpr int KK = KV;      \
-        __VA_ARGS__;                \
-    } break;
-#define UPS_DISPATCH_K(K, ...)                                                                            \
-    switch (K) {                                                                                          \
-        UPS_CASE_K(1, __VA_ARGS__) UPS_CASE_K(2, __VA_ARGS__) UPS_CASE_K(4, __VA_ARGS__)                  \
-        UPS_CASE_K(8, __VA_ARGS__) UPS_CASE_K(16, __VA_ARGS__) UPS_CASE_K(32, __VA_ARGS__)                \
-        UPS_CASE_K(64, __VA_ARGS__)                                                                       \
-        default:                                                                                          \
-            set_error("unsupported pixels-per-thread");                                                   \
-            return UPS_ERR_INVALID_ARG;                                                                   \
-    }
-#define UPS_CASE_P(PV, ...)         \
-    case PV: {                      \
-        constexpr int PP = PV;      \
-        __VA_ARGS__;                \
-    } break;
-#define UPS_DISPATCH_P(P, ...)                                                                            \
-    switch (P) {                                                                                          \
-        UPS_CASE_P(UPS_PREC_KAHAN_F64, __VA_ARGS__)                                                       \
-        UPS_CASE_P(UPS_PREC_F32, __VA_ARGS__) UPS_CASE_P(UPS_PREC_F64, __VA_ARGS__)                       \
-        default:                                                                                          \
-            set_error("unknown precision mode");                                                          \
-            return UPS_ERR_INVALID_ARG;                                                                   \
-    }
-
-template <int K, int PREC>
-static void launch_one_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
-    if (I.world) {
-        if (mode == MODE_ITER)
-            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, true>), dim3(blocks), dim3(kBlock), 0, s, I, a);
-        else
-            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL, true>), dim3(blocks), dim3(kBlock), 0, s, I, a);
-    } else {
-        if (mode == MODE_ITER)
-            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
-        else
-            hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
-    }
-}
-
-static ups_status launch_one(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
-                             hipStream_t s) {
-    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_one_t<KK, PP>(mode, I, a, blocks, s)))
-    UPS_CHECK_HIP(hipGetLastError());
-    return UPS_OK;
-}
-
-template <int K, int PREC>
-static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
-                           hipStream_t s) {
-    if (mode == MODE_ITER)
-        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
-                           n, a);
-    else
-        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
-                           n, a);
-}
-
-ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
-                            const StepArgs &a, int blocks, hipStream_t s) {
-    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_batch_t<KK, PP>(mode, insts, tile_start, n, a, blocks, s)))
-    UPS_CHECK_HIP(hipGetLastError());
-    return UPS_OK;
-}
-
-template <int K, int PREC>
-static void launch_list_t(int mode, const Inst *insts, const Compact *hdr, const int *list, const int *start_l,
-                          const StepArgs &a, int blocks, hipStream_t s) {
-    if (mode == MODE_ITER)
-        hipLaunchKernelGGL((k_icp_batch_list<K, PREC, MODE_ITER>), dim3(blocks), dim3(kBlock), 0, s, insts, hdr, list,
-                           start_l, a);
-    else
-        hipLaunchKernelGGL((k_icp_batch_list<K, PREC, MODE_EVAL>), dim3(blocks), dim3(kBlock), 0, s, insts, hdr, list,
-                           start_l, a);
-}
-
-ups_status launch_icp_batch_list(int K, int prec, int mode, const Inst *insts, const Compact *hdr, const int *list,
-                                 const int *start_l, int n, const StepArgs &a, int blocks, hipStream_t s) {
-    (void)n;
-    if (blocks <= 0) return UPS_OK;
-    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_list_t<KK, PP>(mode, insts, hdr, list, start_l, a, blocks, s)))
-    UPS_CHECK_HIP(hipGetLastError());
-    return UPS_OK;
-}
-
 __global__ void k_activate_batch(const Inst *__restrict__ insts, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) insts[k].state[0].active = 1;
@@ -1015,6 +292,21 @@ static ups_status launch_collapse_one(int prec, int mode, const Inst &I, int par
 // A registration: prepare (init + pyramids), the Gauss-Newton launches level
 // by level, the evaluation launch and the finish launch.  The descriptor
 // carries the state/partials scratch; pixels per thread follow pick_k_single.
+// One iteration or evaluation launch of a single registration: the variant
+// (world frame, IRLS, plain) selects the translation unit that holds it.
+static ups_status launch_one(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
+                             hipStream_t s) {
+    if (I.world) {
+        if (a.irls_delta > 0.f) {
+            set_error("the world-frame variant has no IRLS objective");
+            return UPS_ERR_INVALID_ARG;
+        }
+        return launch_icp_one_world(K, prec, mode, I, a, blocks, s);
+    }
+    if (a.irls_delta > 0.f) return launch_icp_one_irls(K, prec, mode, I, a, blocks, s);
+    return launch_icp_one_plain(K, prec, mode, I, a, blocks, s);
+}
+
 ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_params &p, hipStream_t s) {
     Inst I = I0;
     int Ks[4] = {1, 1, 1, 1};
@@ -1031,6 +323,7 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.cos_theta = p.cos_theta_max;
+    a.irls_delta = p.irls_delta;
     a.min_inliers = p.min_inliers;
     a.stop_norm = p.stop_update_norm;
     int parity = 0;

@@ -43,6 +43,7 @@ struct StepArgs {
     int level, parity, first_of_level, check_max_iters;
     int prev_level;  // level of the previous launch (-1: none), whose partials this launch reduces
     float d_max2, cos_theta, tau2;
+    float irls_delta;  // > 0: inlier terms weighted by 1 / max(|r|, irls_delta)
     int min_inliers;
     double stop_norm;
 };
@@ -73,8 +74,23 @@ ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, con
                                         int32_t *idx, uint8_t *inl, hipStream_t s);
 ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_theta, int precision,
                        hipStream_t s);
+// Iteration / evaluation launches of the ICP kernel.  Batches pick the IRLS
+// instantiation themselves when a.irls_delta > 0; single registrations go
+// through launch_register / launch_eval.  Each variant lives in its own
+// translation unit (ups_icp_iter_*.hip).
 ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
                             const StepArgs &a, int blocks, hipStream_t s);
+ups_status launch_icp_one_plain(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
+                                hipStream_t s);
+ups_status launch_icp_one_world(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
+                                hipStream_t s);
+ups_status launch_icp_one_irls(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
+                               hipStream_t s);
+ups_status launch_icp_batch_irls(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
+                                 const StepArgs &a, int blocks, hipStream_t s);
+ups_status launch_icp_batch_list_irls(int K, int prec, int mode, const Inst *insts, const Compact *hdr,
+                                      const int *list, const int *start_l, int n, const StepArgs &a, int blocks,
+                                      hipStream_t s);
 ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s);
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
 ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,

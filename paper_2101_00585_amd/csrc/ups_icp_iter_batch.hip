@@ -1,0 +1,27 @@
+// Iteration / evaluation launches of a batch (all registrations, or the
+// Compact list of a subset), squared objective; the IRLS objective is handed
+// to its own translation unit.
+#include "ups_icp_kernels.hpp"
+
+namespace ups {
+
+template <int K, int PREC>
+static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
+                           hipStream_t s) {
+    if (mode == MODE_ITER)
+        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_ITER, false>), dim3(blocks), dim3(kBlock), 0, s, insts,
+                           tile_start, n, a);
+    else
+        hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_EVAL, false>), dim3(blocks), dim3(kBlock), 0, s, insts,
+                           tile_start, n, a);
+}
+
+ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
+                            const StepArgs &a, int blocks, hipStream_t s) {
+    if (a.irls_delta > 0.f) return launch_icp_batch_irls(K, prec, mode, insts, tile_start, n, a, blocks, s);
+    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_batch_t<KK, PP>(mode, insts, tile_start, n, a, blocks, s)))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+}  // namespace ups

@@ -1,0 +1,22 @@
+// Iteration / evaluation launches of a single registration, squared
+// objective, keyframe-frame arithmetic (the default path).
+#include "ups_icp_kernels.hpp"
+
+namespace ups {
+
+template <int K, int PREC>
+static void launch_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
+    if (mode == MODE_ITER)
+        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, false, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+    else
+        hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_EVAL, false, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
+}
+
+ups_status launch_icp_one_plain(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
+                                hipStream_t s) {
+    UPS_DISPATCH_P(prec, UPS_DISPATCH_K(K, launch_t<KK, PP>(mode, I, a, blocks, s)))
+    UPS_CHECK_HIP(hipGetLastError());
+    return UPS_OK;
+}
+
+}  // namespace ups

@@ -38,7 +38,8 @@ def test_struct_sizes_match_header():
     # ups_pose: 12 doubles; ups_geom: 2 ints + 4 doubles; result layout fixed by the header
     assert ctypes.sizeof(ups.ups_pose) == 96
     assert ctypes.sizeof(ups.ups_geom) == 40
-    assert ctypes.sizeof(ups.ups_icp_params) == 4 + 16 + 16 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(ups.ups_icp_params) == 4 + 16 + 16 + 4 + 8 + 4 + 4 + 4 + 4  # irls_delta + padding
+    assert ups.ups_icp_params.irls_delta.offset == 56
     assert ups.RESULT_BYTES == 96 + 24 + 16 + 8 + 16 + 21 * 8 + 6 * 8 + 8
     assert ups.NEQ_BYTES == 21 * 8 + 6 * 8 + 8 + 16
     assert ctypes.sizeof(ups.ups_grid_params) == 6 * 4
