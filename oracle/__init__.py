@@ -53,7 +53,7 @@ def _lib():
         _LIB = ctypes.CDLL(so)
         for name in ("orc_project", "orc_raw_normals", "orc_atrous", "orc_panorama_normals", "orc_pyramid_level",
                      "orc_residuals", "orc_normal_equations", "orc_normal_equations_irls", "orc_solve6",
-                     "orc_register", "orc_fuse"):
+                     "orc_register", "orc_fuse", "orc_free_space_violations", "orc_remove_marked"):
             getattr(_LIB, name).restype = ctypes.c_int
     return _LIB
 
@@ -84,6 +84,10 @@ class _IcpResult(ctypes.Structure):
                 ("iters_run", ctypes.c_int32), ("status", ctypes.c_int32), ("level_iters", ctypes.c_int32 * 4),
                 ("JtJ", ctypes.c_double * 21),
                 ("Jtr", ctypes.c_double * 6), ("last_update_norm", ctypes.c_double)]
+
+
+class _ConsistencyParams(ctypes.Structure):
+    _fields_ = [("margin_abs", ctypes.c_double), ("margin_rel", ctypes.c_double), ("min_count", ctypes.c_int32)]
 
 
 class _FuseParams(ctypes.Structure):
@@ -320,3 +324,55 @@ def fuse(sg, scan, kg, kf, kf_count, T, params: FuseParams | None = None):
     _lib().orc_fuse(ctypes.byref(_geom(sg)), _ptr(s), ctypes.byref(_geom(kg)), _ptr(k), _ptr(c), _ptr(pose12(T)),
                     ctypes.byref(pc))
     return k, c
+
+
+@dataclass
+class ConsistencyParams:
+    """Readings for the moving-object check across keyframes (Section III-C):
+    a sample is contradicted when the other keyframe saw more than
+    max(margin_abs, margin_rel * range) beyond it on every ray of a 3x3
+    neighbourhood, each with at least ``min_count`` fused samples."""
+    margin_abs: float = 0.2
+    margin_rel: float = 0.02
+    min_count: int = 1
+
+    def _c(self):
+        return _ConsistencyParams(self.margin_abs, self.margin_rel, self.min_count)
+
+
+def free_space_violations(ga, a, gb, b, b_count, T_ba, params: ConsistencyParams | None = None) -> np.ndarray:
+    """Mask [rows_a, cols_a] of keyframe A's samples that keyframe B saw
+    through; T_ba maps A's frame into B's.  b_count None: any count votes."""
+    p = params or ConsistencyParams()
+    sa = _f64(a, (ga.rows, ga.cols, 4))
+    sb = _f64(b, (gb.rows, gb.cols, 4))
+    cb = None
+    if b_count is not None:
+        cb = np.ascontiguousarray(np.asarray(b_count, dtype=np.uint16).reshape(gb.rows, gb.cols))
+    mask = np.zeros((ga.rows, ga.cols), np.uint8)
+    pc = p._c()
+    _lib().orc_free_space_violations(ctypes.byref(_geom(ga)), _ptr(sa), ctypes.byref(_geom(gb)), _ptr(sb),
+                                     None if cb is None else _ptr(cb), _ptr(pose12(T_ba)), ctypes.byref(pc),
+                                     _ptr(mask))
+    return mask.astype(bool)
+
+
+def keyframe_consistency(ga, a, a_count, gb, b, b_count, T_ba, params: ConsistencyParams | None = None):
+    """The mutual check: both masks from the unmodified keyframes, then the
+    marked samples of each removed.  Returns (a, a_count, b, b_count, mask_a,
+    mask_b) as new arrays."""
+    mask_a = free_space_violations(ga, a, gb, b, b_count, T_ba, params)
+    T = pose44(pose12(T_ba))
+    T_ab = np.eye(4)
+    T_ab[:3, :3] = T[:3, :3].T
+    T_ab[:3, 3] = -T[:3, :3].T @ T[:3, 3]
+    mask_b = free_space_violations(gb, b, ga, a, a_count, T_ab, params)
+    out = []
+    for g, s, c, m in ((ga, a, a_count, mask_a), (gb, b, b_count, mask_b)):
+        s2 = _f64(s, (g.rows, g.cols, 4)).copy()
+        c2 = None if c is None else np.ascontiguousarray(np.asarray(c, dtype=np.uint16).reshape(g.rows, g.cols)).copy()
+        mm = np.ascontiguousarray(m.astype(np.uint8))
+        _lib().orc_remove_marked(ctypes.byref(_geom(g)), _ptr(s2), None if c2 is None else _ptr(c2), _ptr(mm))
+        out += [s2, c2]
+    return out[0], out[1], out[2], out[3], mask_a, mask_b
+

@@ -640,3 +640,73 @@ int orc_fuse(const orc_geom *sg, const double *scan, const orc_geom *kg, double 
     free(was_empty);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Moving-object filtering across keyframes (Section III-C: the keyframes    */
+/* together hold several hypotheses of occupancy, and a mutual consistency   */
+/* check at keyframe switches removes what moved).  Reading: a sample of     */
+/* keyframe A is inconsistent with keyframe B when B looked through the      */
+/* place where A's sample lies.  A's point x = r u(i, j) is mapped into B    */
+/* (y = T_ba x) and projected to B's pixel (i', j'); the sample is marked    */
+/* when every pixel of B's 3x3 neighbourhood of (i', j') (columns wrap; a    */
+/* row outside the image ends the test) holds a valid range with at least    */
+/* min_count samples (any count when b_count is NULL) that exceeds |y| by    */
+/* more than max(margin_abs, margin_rel |y|).  The neighbourhood keeps       */
+/* samples at B's depth edges, where the nearest pixel can fall on the far   */
+/* side of the edge.                                                         */
+/* ------------------------------------------------------------------------ */
+
+int orc_free_space_violations(const orc_geom *ga, const double *a, const orc_geom *gb, const double *b,
+                              const uint16_t *b_count, const double T_ba[12], const orc_consistency_params *p,
+                              uint8_t *mask_a) {
+    for (int i = 0; i < ga->rows; i++) {
+        for (int j = 0; j < ga->cols; j++) {
+            size_t px = (size_t)i * ga->cols + j;
+            mask_a[px] = 0;
+            double r = a[4 * px + 3];
+            if (!range_ok(ga, r)) continue;
+            double u[3], x[3], y[3];
+            orc_ray(ga, i, j, u);
+            for (int k = 0; k < 3; k++) x[k] = r * u[k];
+            transform(T_ba, x, y);
+            int32_t bi, bj;
+            if (!orc_project(gb, y, &bi, &bj)) continue;
+            double rho = norm3(y);
+            double margin = p->margin_rel * rho > p->margin_abs ? p->margin_rel * rho : p->margin_abs;
+            int seen_through = 1;
+            for (int di = -1; di <= 1 && seen_through; di++) {
+                int ii = bi + di;
+                if (ii < 0 || ii >= gb->rows) {
+                    seen_through = 0;
+                    break;
+                }
+                for (int dj = -1; dj <= 1; dj++) {
+                    int jj = (bj + dj + gb->cols) % gb->cols;
+                    size_t q = (size_t)ii * gb->cols + jj;
+                    double rb = b[4 * q + 3];
+                    int votes = b_count == NULL || b_count[q] >= p->min_count;
+                    if (!(range_ok(gb, rb) && votes && rb > rho + margin)) {
+                        seen_through = 0;
+                        break;
+                    }
+                }
+            }
+            mask_a[px] = (uint8_t)seen_through;
+        }
+    }
+    return 0;
+}
+
+/* Removal of marked samples: surfel (0, 0, 0, 0), count 0 (count may be NULL). */
+int orc_remove_marked(const orc_geom *g, double *surfel, uint16_t *count, const uint8_t *mask) {
+    size_t n = (size_t)g->rows * g->cols;
+    int removed = 0;
+    for (size_t px = 0; px < n; px++) {
+        if (!mask[px]) continue;
+        for (int k = 0; k < 4; k++) surfel[4 * px + k] = 0.0;
+        if (count) count[px] = 0;
+        removed++;
+    }
+    return removed;
+}
+

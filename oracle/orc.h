@@ -62,6 +62,11 @@ typedef struct {
     int32_t max_count;
 } orc_fuse_params;
 
+typedef struct {
+    double margin_abs, margin_rel; /* free-space margin max(margin_abs, margin_rel * range) */
+    int32_t min_count;             /* samples a pixel of the other keyframe needs to vote */
+} orc_consistency_params;
+
 enum { ORC_CONVERGED = 0, ORC_MAX_ITERS = 1, ORC_DEGENERATE = 2, ORC_NO_INLIERS = 3 };
 
 void orc_ray(const orc_geom *g, int i, int j, double u[3]);
@@ -85,6 +90,11 @@ int orc_register(const orc_geom *sg, const double *scan, const orc_geom *kg, con
                  const double init[12], const orc_icp_params *p, orc_icp_result *res);
 int orc_fuse(const orc_geom *sg, const double *scan, const orc_geom *kg, double *kf, uint16_t *kf_count,
              const double T[12], const orc_fuse_params *p);
+
+int orc_free_space_violations(const orc_geom *ga, const double *a, const orc_geom *gb, const double *b,
+                              const uint16_t *b_count, const double T_ba[12], const orc_consistency_params *p,
+                              uint8_t *mask_a);
+int orc_remove_marked(const orc_geom *g, double *surfel, uint16_t *count, const uint8_t *mask);
 
 #ifdef __cplusplus
 }

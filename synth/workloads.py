@@ -198,3 +198,57 @@ def outlier_patches(depth, seed: int, frac: float = 0.2, h: int = 8, w: int = 16
         blk = d[i:i + h, j:j + w]
         d[i:i + h, j:j + w] = np.where(blk > 0, blk + off, blk)
     return d
+
+
+# ----------------------------------------------------------------------------
+# two keyframes of one room with objects that moved between them
+# ----------------------------------------------------------------------------
+
+MOVER_SIZE = (0.6, 0.6, 1.8)  # a person-sized box, metres
+
+
+def _movers(rng, n, room, avoid, min_dist=1.5):
+    out = []
+    sx, sy, sz = MOVER_SIZE
+    tries = 0
+    while len(out) < n and tries < 10000:
+        tries += 1
+        cx = rng.uniform(room[0] + sx, room[3] - sx)
+        cy = rng.uniform(room[1] + sy, room[4] - sy)
+        b = np.array([cx - sx / 2, cy - sy / 2, 0.0, cx + sx / 2, cy + sy / 2, sz])
+        lo, hi = b[:3], b[3:]
+        if any(np.linalg.norm(np.maximum(np.maximum(lo - p, 0), p - hi)) < min_dist for p in avoid):
+            continue
+        out.append(b)
+    return np.array(out).reshape(-1, 6)
+
+
+def moving_objects_pair(seed: int, rows: int = 64, cols: int = 1024, n_movers: int = 3, baseline: float = 3.0,
+                        noise: float = 0.01, dtype=np.float32):
+    """Two keyframes of the box room ``baseline`` metres apart.  Person-sized
+    boxes stand in the room only when keyframe A is taken (``n_movers`` of
+    them) and others only when B is taken.  Returns dict(geom, kf_a, kf_b,
+    T_ba (A frame -> B frame), T_world_a, T_world_b, mover_a, mover_b) where
+    mover_* marks the pixels whose return comes from a mover (noise-free
+    renders with and without the movers differ)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 3571))
+    pa = np.array([rng.uniform(-5, 5), rng.uniform(-2, 2), 1.5])
+    d = _unit_horizontal(rng) * baseline
+    pb = pa + np.array([d[0], d[1], 0.0])
+    pb[0] = float(np.clip(pb[0], -8.0, 8.0))
+    pb[1] = float(np.clip(pb[1], -3.5, 3.5))
+    T_w_a = se3(rot_z(rng.uniform(-math.pi, math.pi)), pa)
+    T_w_b = se3(rot_z(rng.uniform(-math.pi, math.pi)), pb)
+    static = room_scene(seed, sensor_positions=[pa, pb], n_boxes=3)
+    room = static.room
+    mov_a = _movers(rng, n_movers, room, [pa, pb])
+    mov_b = _movers(rng, n_movers, room, [pa, pb])
+    g = lidar_geom(rows, cols)
+    scene_a = type(static)(room=room, boxes=np.vstack([static.boxes, mov_a]), kind="room")
+    scene_b = type(static)(room=room, boxes=np.vstack([static.boxes, mov_b]), kind="room")
+    kf_a = render(scene_a, g, T_w_a, noise, seed * 2 + 11, dtype=dtype)
+    kf_b = render(scene_b, g, T_w_b, noise, seed * 2 + 12, dtype=dtype)
+    mover_a = np.abs(render(scene_a, g, T_w_a, dtype=np.float64) - render(static, g, T_w_a, dtype=np.float64)) > 1e-9
+    mover_b = np.abs(render(scene_b, g, T_w_b, dtype=np.float64) - render(static, g, T_w_b, dtype=np.float64)) > 1e-9
+    return dict(geom=g, kf_a=kf_a, kf_b=kf_b, T_ba=inv(T_w_b) @ T_w_a, T_world_a=T_w_a, T_world_b=T_w_b,
+                mover_a=mover_a, mover_b=mover_b, static=static, movers_a=mov_a, movers_b=mov_b)
