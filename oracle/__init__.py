@@ -376,3 +376,31 @@ def keyframe_consistency(ga, a, a_count, gb, b, b_count, T_ba, params: Consisten
         out += [s2, c2]
     return out[0], out[1], out[2], out[3], mask_a, mask_b
 
+
+
+LOOP_NONE, LOOP_WEAK, LOOP_STRONG = 0, 1, 2
+
+
+def loop_closure_classes(ratios, statuses, new_keyframe_ratio):
+    """Section III-C: a loop-closure registration whose quality (inlier
+    ratio) is higher than the threshold for seeking a new keyframe is a strong
+    closure (its keyframe becomes the current one); one higher than 75 % of it
+    is a weak closure (a pose-graph edge only); registrations that failed
+    (status 2 degenerate, 3 too few inliers) close nothing.  Returns the
+    classes and the strong closure with the highest ratio (first of equals),
+    -1 when there is none."""
+    classes = []
+    best, best_ratio = -1, None
+    for k, (q, st) in enumerate(zip(ratios, statuses)):
+        if st in (2, 3):
+            c = LOOP_NONE
+        elif q > new_keyframe_ratio:
+            c = LOOP_STRONG
+        elif q > 0.75 * new_keyframe_ratio:
+            c = LOOP_WEAK
+        else:
+            c = LOOP_NONE
+        classes.append(c)
+        if c == LOOP_STRONG and (best_ratio is None or q > best_ratio):
+            best, best_ratio = k, q
+    return np.array(classes, dtype=np.int32), best
