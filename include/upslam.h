@@ -198,6 +198,51 @@ ups_status ups_fuse_scan(ups_context *ctx, const ups_geom *scan_g, const float *
                          const ups_geom *kf_g, float *kf_surfel_d, uint16_t *kf_count_d, const ups_pose *T_d,
                          const ups_fuse_params *p, void *stream);
 
+/* ---- keyframe management (Section III-C) -------------------------------- */
+
+/* Moving-object check between two keyframes, run when the current keyframe
+ * changes: the keyframes together record which space was seen empty, so a
+ * sample of one that the other looked through belongs to something that
+ * moved.  A sample of keyframe A (valid range r at pixel (i, j), point
+ * x = r u(i, j)) is removed when, with y = T_ba x projected to B's pixel
+ * (i', j'), every pixel of B's 3x3 neighbourhood of (i', j') (columns wrap; a
+ * neighbourhood that leaves B's rows keeps the sample) holds a valid range
+ * exceeding |y| + max(margin_abs, margin_rel |y|) with at least min_count
+ * fused samples (b_count_d NULL: any count).  Mutual when b_mask_d is given:
+ * B's samples are tested against A with T_ba^-1, both from the unmodified
+ * images, then the marked samples of both are removed.
+ *   T_ba_d      device pose mapping A's frame into B's;
+ *   a/b_surfel  device float4 [rows][cols] surfel images, modified in place:
+ *               removed samples become (0, 0, 0, 0);
+ *   a/b_count   device uint16 [rows][cols] sample counts (may be NULL),
+ *               removed samples get count 0;
+ *   a/b_mask    caller-owned uint8 [rows][cols] outputs, 1 = removed;
+ *               b_mask_d NULL: only A is tested and modified;
+ *   removed_d   device int32 [2] (may be NULL): numbers removed from A and B.
+ * Enqueues three kernels on `stream`; the images must not alias. */
+typedef struct {
+    float margin_abs, margin_rel; /* metres, fraction of the range */
+    int32_t min_count;            /* samples a voting pixel needs */
+} ups_consistency_params;
+
+ups_status ups_keyframe_consistency(ups_context *ctx, const ups_geom *a_g, float *a_surfel_d, uint16_t *a_count_d,
+                                    const ups_geom *b_g, float *b_surfel_d, uint16_t *b_count_d,
+                                    const ups_pose *T_ba_d, const ups_consistency_params *p, uint8_t *a_mask_d,
+                                    uint8_t *b_mask_d, int32_t *removed_d, void *stream);
+
+/* Loop-closure classes (Section III-C) for n registrations of the current
+ * scan against neighbouring keyframes (results_d, device): STRONG when the
+ * inlier ratio exceeds new_keyframe_ratio (the quality below which a new
+ * keyframe is sought; the neighbour becomes the current keyframe), WEAK when
+ * it exceeds 3/4 of it (a pose-graph edge only), NONE otherwise and for
+ * registrations that ended UPS_DEGENERATE or UPS_NO_INLIERS.  class_d: device
+ * int32 [n]; best_d (device int32, may be NULL): the STRONG closure with the
+ * highest ratio, the lowest index among equals, -1 when there is none.  One
+ * kernel on `stream`. */
+enum { UPS_LOOP_NONE = 0, UPS_LOOP_WEAK = 1, UPS_LOOP_STRONG = 2 };
+ups_status ups_classify_loop_closures(ups_context *ctx, int32_t n, const ups_icp_result *results_d,
+                                      double new_keyframe_ratio, int32_t *class_d, int32_t *best_d, void *stream);
+
 /* Projective correspondences at a fixed pose at level 0 (Section III-B):
  * kf_index_d[rows*cols] = keyframe pixel index i*cols+j the scan point projects
  * to, or -1 (no scan surfel or outside the keyframe's rows); inlier_d = 1 iff

@@ -117,6 +117,8 @@ def load():
         "ups_batch_fallback_run": [_P, _P, _P, _P],
         "ups_batch_grid_search": [_P, _P, _P, _P, _P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
+        "ups_keyframe_consistency": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
+        "ups_classify_loop_closures": [_P, ctypes.c_int32, _P, ctypes.c_double, _P, _P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
         "ups_batch_time_iteration": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_float)],
     }
@@ -377,6 +379,78 @@ def fuse_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, kf_count
                               else _dev_ptr(kf_count, torch.uint16, "keyframe count"),
                               _dev_ptr(T_t, torch.float64, "pose"), ctypes.byref(p), _stream()))
     return kf_surfel, kf_count
+
+
+class ups_consistency_params(ctypes.Structure):
+    _fields_ = [("margin_abs", ctypes.c_float), ("margin_rel", ctypes.c_float), ("min_count", ctypes.c_int32)]
+
+
+LOOP_NONE, LOOP_WEAK, LOOP_STRONG = 0, 1, 2
+
+
+@dataclass
+class ConsistencyParams:
+    """Moving-object check across keyframes: a sample is removed when the other
+    keyframe saw more than max(margin_abs, margin_rel * range) beyond it on
+    every ray of a 3x3 neighbourhood, each with >= min_count samples."""
+    margin_abs: float = 0.2
+    margin_rel: float = 0.02
+    min_count: int = 1
+
+    def c(self):
+        return ups_consistency_params(self.margin_abs, self.margin_rel, self.min_count)
+
+
+def _count_ptr(t, what):
+    torch = _torch()
+    if t is None:
+        return None
+    return _dev_ptr(t, torch.int16 if t.dtype == torch.int16 else torch.uint16, what)
+
+
+def keyframe_consistency(ctx: Context, a_geom, a_surfel, a_count, b_geom, b_surfel, b_count, T_ba,
+                         params: ConsistencyParams | None = None, mutual: bool = True, a_mask=None, b_mask=None,
+                         removed=None):
+    """Remove in place the samples of keyframe A (and of B when ``mutual``)
+    that the other keyframe looked through; counts may be None.  Returns the
+    device masks (uint8, 1 = removed; B's is None unless mutual) and the
+    device int32 [2] removal counts."""
+    torch = _torch()
+    dev = a_surfel.device
+    p = (params or ConsistencyParams()).c()
+    T_t = T_ba if isinstance(T_ba, torch.Tensor) else pose_tensor(T_ba, dev)
+    if a_mask is None:
+        a_mask = torch.empty((a_geom.rows, a_geom.cols), dtype=torch.uint8, device=dev)
+    if mutual and b_mask is None:
+        b_mask = torch.empty((b_geom.rows, b_geom.cols), dtype=torch.uint8, device=dev)
+    if not mutual:
+        b_mask = None
+    if removed is None:
+        removed = torch.empty(2, dtype=torch.int32, device=dev)
+    ga, gb = geom_c(a_geom), geom_c(b_geom)
+    _check(_LIB.ups_keyframe_consistency(ctx.handle, ctypes.byref(ga), _dev_ptr(a_surfel, torch.float32, "A surfel"),
+                                         _count_ptr(a_count, "A count"), ctypes.byref(gb),
+                                         _dev_ptr(b_surfel, torch.float32, "B surfel"), _count_ptr(b_count, "B count"),
+                                         _dev_ptr(T_t, torch.float64, "pose"), ctypes.byref(p),
+                                         _dev_ptr(a_mask, torch.uint8, "A mask"),
+                                         None if b_mask is None else _dev_ptr(b_mask, torch.uint8, "B mask"),
+                                         _dev_ptr(removed, torch.int32, "removed"), _stream()))
+    a_mask._keep = T_t
+    return a_mask, b_mask, removed
+
+
+def classify_loop_closures(ctx: Context, results, new_keyframe_ratio: float, n: int | None = None):
+    """Classes (LOOP_NONE / LOOP_WEAK / LOOP_STRONG, device int32 [n]) of the
+    registrations in the device results buffer, and the index of the best
+    strong closure (device int32 [1], -1 if none)."""
+    torch = _torch()
+    n = results.shape[0] if n is None else n
+    cls = torch.empty(n, dtype=torch.int32, device=results.device)
+    best = torch.empty(1, dtype=torch.int32, device=results.device)
+    _check(_LIB.ups_classify_loop_closures(ctx.handle, int(n), _dev_ptr(results, torch.uint8, "results"),
+                                           float(new_keyframe_ratio), _dev_ptr(cls, torch.int32, "class"),
+                                           _dev_ptr(best, torch.int32, "best"), _stream()))
+    return cls, best
 
 
 def correspondences(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T, d_max=0.5,

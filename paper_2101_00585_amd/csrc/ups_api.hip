@@ -24,18 +24,6 @@ ups_status check_ptr(const void *p, size_t align, const char *what) {
     return UPS_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit DeviceGuard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 static ups_status check_geom(const ups_geom *g, const char *what) {
     UPS_REQUIRE(g != nullptr, std::string(what) + " geometry is null");

@@ -50,18 +50,6 @@ constexpr int kListBlocks = 512, kListSolveBlocks = 32;
 
 namespace {
 
-struct Guard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit Guard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~Guard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 void free_batch(ups_batch *b) {
     (void)hipFree(b->d_inst);
@@ -105,7 +93,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     }
     UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
     UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     const int L = p->levels, s = 1 << (L - 1);
     int64_t total_scan = 0, total_kf = 0, max_npix = 0;
@@ -279,7 +267,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
 
 void ups_batch_destroy(ups_batch *b) {
     if (!b) return;
-    Guard dg(b->device);
+    DeviceGuard dg(b->device);
     free_batch(b);
 }
 
@@ -288,7 +276,7 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
     UPS_REQUIRE(ctx && b && us_per_launch, "null argument");
     UPS_REQUIRE(level >= 0 && level < b->p.levels, "level out of range");
     UPS_REQUIRE(n_launches >= 1 && n_launches <= 10000, "n_launches must be in [1, 10000]");
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     hipStream_t s = (hipStream_t)stream;
     ups ::StepArgs a;
@@ -332,7 +320,7 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
     UPS_REQUIRE(ctx && b && p, "null argument");
     UPS_REQUIRE(p->atrous_levels >= 1 && p->atrous_levels <= 3, "batched normals need atrous_levels in [1, 3]");
     UPS_REQUIRE(p->sigma_n > 0.f && p->sigma_r > 0.f && p->max_rel_jump >= 0.f, "sigmas must be > 0");
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     if (b->n_nimg == 0) return UPS_OK;
     return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p, (hipStream_t)stream);
@@ -407,7 +395,7 @@ ups_status ups_register_batch(ups_context *ctx, ups_batch *b, const ups_pose *in
     ups_status st;
     if ((st = check_ptr(init_d, 8, "init poses")) != UPS_OK) return st;
     if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     return register_batch_impl(b, init_d, nullptr, results_d, (hipStream_t)stream);
 }
@@ -425,7 +413,7 @@ ups_status ups_batch_grid_search(ups_context *ctx, ups_batch *b, const ups_grid_
     if ((st = check_ptr(scores_d, 4, "scores")) != UPS_OK) return st;
     if ((st = check_ptr(best_d, 8, "best poses")) != UPS_OK) return st;
     if (best_score_d && (st = check_ptr(best_score_d, 4, "best scores")) != UPS_OK) return st;
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     hipStream_t s = (hipStream_t)stream;
     const int n = b->n, l = gp->level;
@@ -450,7 +438,7 @@ ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_in
     ups_status st;
     if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
     if (count_d && (st = check_ptr(count_d, 4, "count")) != UPS_OK) return st;
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     return launch_fallback_plan(b->n, results_d, min_inlier_ratio, b->d_tile_start, b->mask, b->comp, b->comp_list,
                                 b->comp_start, count_d, (hipStream_t)stream);
@@ -460,7 +448,7 @@ ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result
     UPS_REQUIRE(ctx && b, "null argument");
     ups_status st;
     if ((st = check_ptr(results_d, 8, "results")) != UPS_OK) return st;
-    Guard dg(ctx->device);
+    DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     hipStream_t s = (hipStream_t)stream;
     if ((st = register_batch_impl(b, b->ident, b->mask, b->alt, s)) != UPS_OK) return st;

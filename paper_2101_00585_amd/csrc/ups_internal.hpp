@@ -70,6 +70,20 @@ namespace ups {
 
 constexpr int kPartialStride = 32;  // doubles per block partial
 
+// Makes `dev` the current device for the scope and restores the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
 // Validate a geometry and return its device view at pyramid level `level`
 // (ray tables are uploaded on first use of the geometry).
 ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream_t stream, DGeom *out);

@@ -56,18 +56,6 @@ const Layout &layout() {
     return L;
 }
 
-struct Guard {
-    int prev = -1;
-    hipError_t err = hipSuccess;
-    explicit Guard(int dev) {
-        err = hipGetDevice(&prev);
-        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
-    }
-    ~Guard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 // One range image the input is taken from: range of pixel (i, j) at
 // r[(i * cols + j) * stride].
@@ -200,7 +188,7 @@ ups_status ups_proposal_create(ups_context *ctx, int32_t max_batch, ups_proposal
     UPS_REQUIRE(ctx && out, "null argument");
     UPS_REQUIRE(max_batch >= 1 && max_batch <= 65536, "max_batch must be in [1, 65536]");
     *out = nullptr;
-    Guard g(ctx->device);
+    DeviceGuard g(ctx->device);
     UPS_CHECK_HIP(g.err);
     const Layout &L = layout();
     ups_proposal *p = new ups_proposal();
@@ -251,7 +239,7 @@ ups_status ups_proposal_create(ups_context *ctx, int32_t max_batch, ups_proposal
 
 void ups_proposal_destroy(ups_proposal *p) {
     if (!p) return;
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     (void)hipDeviceSynchronize();
     free_prop(p);
 }
@@ -259,7 +247,7 @@ void ups_proposal_destroy(ups_proposal *p) {
 ups_status ups_proposal_set_params(ups_proposal *p, const float *params_h, int64_t n) {
     UPS_REQUIRE(p && params_h, "null argument");
     UPS_REQUIRE(n == layout().total, "parameter count mismatch");
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     UPS_CHECK_HIP(hipMemcpy(p->params, params_h, n * sizeof(float), hipMemcpyHostToDevice));
     UPS_CHECK_HIP(hipMemset(p->m, 0, n * sizeof(float)));
@@ -274,7 +262,7 @@ ups_status ups_proposal_set_params(ups_proposal *p, const float *params_h, int64
 ups_status ups_proposal_get_params(ups_proposal *p, float *params_h, int64_t n) {
     UPS_REQUIRE(p && params_h, "null argument");
     UPS_REQUIRE(n == layout().total, "parameter count mismatch");
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     UPS_CHECK_HIP(hipDeviceSynchronize());
     UPS_CHECK_HIP(hipMemcpy(params_h, p->params, n * sizeof(float), hipMemcpyDeviceToHost));
@@ -284,7 +272,7 @@ ups_status ups_proposal_get_params(ups_proposal *p, float *params_h, int64_t n) 
 ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n) {
     UPS_REQUIRE(p && grads_h, "null argument");
     UPS_REQUIRE(n == layout().total, "parameter count mismatch");
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     UPS_CHECK_HIP(hipDeviceSynchronize());
     UPS_CHECK_HIP(hipMemcpy(grads_h, p->grads, n * sizeof(float), hipMemcpyDeviceToHost));
@@ -308,7 +296,7 @@ ups_status ups_proposal_plan_input(ups_proposal *p, int32_t n, const ups_range_i
             items[b].img[c] = RangeImg{im.range_d, im.rows, im.cols, im.stride, im.r_min, im.r_max};
         }
     }
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     UPS_CHECK_HIP(hipMemcpy(p->d_items, items.data(), n * sizeof(PropItem), hipMemcpyHostToDevice));
     p->n_items = n;
@@ -321,7 +309,7 @@ ups_status ups_proposal_input(ups_proposal *p, uint16_t *x_d, void *stream) {
     ups_status st;
     uint16_t *x = x_d ? x_d : p->act;
     if ((st = check_ptr(x, 8, "input")) != UPS_OK) return st;
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     const int total = p->n_items * kRows * kCols;
     hipLaunchKernelGGL(k_prop_input, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream, p->d_items,
@@ -337,7 +325,7 @@ ups_status ups_proposal_forward(ups_proposal *p, int32_t n, const uint16_t *x_d,
     const uint16_t *x = x_d ? x_d : p->act;
     if ((st = check_ptr(x, 8, "input")) != UPS_OK) return st;
     if ((st = check_ptr(y_d, 4, "output")) != UPS_OK) return st;
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     return forward_impl(p, n, x, y_d, (hipStream_t)stream);
 }
@@ -348,7 +336,7 @@ ups_status ups_proposal_poses(ups_proposal *p, int32_t n, const float *y_d, ups_
     if ((st = check_n(p, n)) != UPS_OK) return st;
     if ((st = check_ptr(y_d, 4, "output")) != UPS_OK) return st;
     if ((st = check_ptr(poses_d, 8, "poses")) != UPS_OK) return st;
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     hipLaunchKernelGGL(k_prop_pose, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)stream, n, y_d, poses_d);
     UPS_CHECK_HIP(hipGetLastError());
@@ -364,7 +352,7 @@ ups_status ups_proposal_train_step(ups_proposal *p, int32_t n, const uint16_t *x
     if ((st = check_ptr(x, 8, "input")) != UPS_OK) return st;
     if ((st = check_ptr(target_d, 4, "target")) != UPS_OK) return st;
     UPS_REQUIRE(std::isfinite(lr) && lr >= 0.f, "lr must be finite and >= 0");
-    Guard g(p->device);
+    DeviceGuard g(p->device);
     UPS_CHECK_HIP(g.err);
     hipStream_t s = (hipStream_t)stream;
     const Layout &L = layout();

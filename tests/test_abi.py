@@ -44,6 +44,8 @@ def test_struct_sizes_match_header():
     assert ups.NEQ_BYTES == 21 * 8 + 6 * 8 + 8 + 16
     assert ctypes.sizeof(ups.ups_grid_params) == 6 * 4
     assert ctypes.sizeof(ups.ups_range_image) == 8 + 3 * 4 + 2 * 4 + 4  # pointer, 3 ints, 2 floats, padding
+    assert ctypes.sizeof(ups.ups_consistency_params) == 3 * 4
+    assert (ups.LOOP_NONE, ups.LOOP_WEAK, ups.LOOP_STRONG) == (0, 1, 2)
 
 
 def test_last_error_without_gpu(lib):
@@ -65,3 +67,9 @@ def test_invalid_arguments_rejected_on_host(lib):
     out = ctypes.c_void_p()
     rc = L.ups_context_create(ctypes.byref(out), 0, 10, 0, 0)
     assert rc == -1 and not out.value
+    cp = ups.ConsistencyParams().c()
+    rc = L.ups_keyframe_consistency(None, ctypes.byref(g), None, None, ctypes.byref(g), None, None, None,
+                                    ctypes.byref(cp), None, None, None, None)
+    assert rc == -1
+    rc = L.ups_classify_loop_closures(None, 4, None, 0.5, None, None, None)
+    assert rc == -1
