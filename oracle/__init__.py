@@ -53,7 +53,8 @@ def _lib():
         _LIB = ctypes.CDLL(so)
         for name in ("orc_project", "orc_raw_normals", "orc_atrous", "orc_panorama_normals", "orc_pyramid_level",
                      "orc_residuals", "orc_normal_equations", "orc_normal_equations_irls", "orc_solve6",
-                     "orc_register", "orc_fuse", "orc_free_space_violations", "orc_remove_marked"):
+                     "orc_register", "orc_fuse", "orc_free_space_violations", "orc_remove_marked",
+                     "orc_splat_sweep"):
             getattr(_LIB, name).restype = ctypes.c_int
     return _LIB
 
@@ -404,3 +405,18 @@ def loop_closure_classes(ratios, statuses, new_keyframe_ratio):
         if c == LOOP_STRONG and (best_ratio is None or q > best_ratio):
             best, best_ratio = k, q
     return np.array(classes, dtype=np.int32), best
+
+
+def splat_sweep(raw_g, raw, col_T, out_g) -> np.ndarray:
+    """Panorama of out_g from a sweep (range image of raw_g whose column j
+    was measured in the frame that the 4x4 col_T[j] maps into the reference
+    frame; None: all identity): nearest range per pixel, 0 where empty."""
+    r = _f64(raw, (raw_g.rows, raw_g.cols))
+    C = None
+    if col_T is not None:
+        C = np.ascontiguousarray(np.stack([pose12(T) for T in np.asarray(col_T, np.float64)]))
+    out = np.zeros((out_g.rows, out_g.cols))
+    _lib().orc_splat_sweep(ctypes.byref(_geom(raw_g)), _ptr(r), None if C is None else _ptr(C),
+                           ctypes.byref(_geom(out_g)), _ptr(out))
+    return out
+

@@ -710,3 +710,48 @@ int orc_remove_marked(const orc_geom *g, double *surfel, uint16_t *count, const 
     return removed;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Panorama formation (Section III-A): the measurements of one sweep, each   */
+/* taken at its own time, are moved into the frame of a single instant and  */
+/* projected into a panoramic image.  raw: the sweep as a range image of     */
+/* raw_g (row = beam, column = firing); col_T + 12 j maps column j's frame    */
+/* into the reference frame (NULL: identity for every column).  A valid      */
+/* measurement r at (i, j) gives x = r u(i, j), y = C_j x; y's pixel of out_g */
+/* keeps the nearest |y| (the smaller raw index among equal ranges); pixels   */
+/* nothing reaches are 0, and so is every |y| outside out_g's valid ranges.   */
+/* ------------------------------------------------------------------------ */
+
+int orc_splat_sweep(const orc_geom *raw_g, const double *raw, const double *col_T, const orc_geom *out_g,
+                    double *out) {
+    size_t nout = (size_t)out_g->rows * out_g->cols;
+    int64_t *win = (int64_t *)malloc(nout * sizeof(int64_t));
+    for (size_t k = 0; k < nout; k++) {
+        out[k] = 0.0;
+        win[k] = -1;
+    }
+    static const double I12[12] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0};
+    for (int i = 0; i < raw_g->rows; i++) {
+        for (int j = 0; j < raw_g->cols; j++) {
+            int64_t k = (int64_t)i * raw_g->cols + j;
+            double r = raw[k];
+            if (!range_ok(raw_g, r)) continue;
+            const double *C = col_T ? col_T + 12 * (size_t)j : I12;
+            double u[3], x[3], y[3];
+            orc_ray(raw_g, i, j, u);
+            for (int a = 0; a < 3; a++) x[a] = r * u[a];
+            transform(C, x, y);
+            double ry = norm3(y);
+            if (!range_ok(out_g, ry)) continue;
+            int32_t oi, oj;
+            if (!orc_project(out_g, y, &oi, &oj)) continue;
+            size_t q = (size_t)oi * out_g->cols + oj;
+            if (win[q] < 0 || ry < out[q] || (ry == out[q] && k < win[q])) {
+                out[q] = ry;
+                win[q] = k;
+            }
+        }
+    }
+    free(win);
+    return 0;
+}
+

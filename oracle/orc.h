@@ -95,6 +95,8 @@ int orc_free_space_violations(const orc_geom *ga, const double *a, const orc_geo
                               const uint16_t *b_count, const double T_ba[12], const orc_consistency_params *p,
                               uint8_t *mask_a);
 int orc_remove_marked(const orc_geom *g, double *surfel, uint16_t *count, const uint8_t *mask);
+int orc_splat_sweep(const orc_geom *raw_g, const double *raw, const double *col_T, const orc_geom *out_g,
+                    double *out);
 
 #ifdef __cplusplus
 }

@@ -304,3 +304,29 @@ def render(scene: Scene, geom: Geom, T_world_sensor, noise_sigma: float = 0.0, n
             nrm[out == 0] = 0.0
         return out, nrm
     return out
+
+
+def render_sweep(scene: Scene, geom: Geom, T_world_cols, noise_sigma: float = 0.0, noise_seed: int | None = None,
+                 dtype=np.float32, threads: int | None = None):
+    """Ray-cast a sweep taken while the sensor moves: column j (azimuth
+    2 pi j / cols, every row) is captured from its own pose T_world_cols[j]
+    (array [cols, 4, 4]).  Range image as ``render`` returns it."""
+    T = np.asarray(T_world_cols, dtype=np.float64).reshape(geom.cols, 4, 4)
+    R = np.ascontiguousarray(T[:, :3, :3].reshape(geom.cols, 9))
+    o = np.ascontiguousarray(T[:, :3, 3])
+    rng_ = np.zeros((geom.rows, geom.cols), dtype=np.float64)
+    sc, keep = scene._c()
+    g = _GeomC(geom.rows, geom.cols, geom.el_top, geom.d_el, geom.r_max)
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    _lib().syn_render_sweep(ctypes.byref(sc), ctypes.byref(g), R.ctypes.data_as(ctypes.c_void_p),
+                            o.ctypes.data_as(ctypes.c_void_p), rng_.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.c_int(threads))
+    del keep
+    if noise_sigma > 0:
+        rng = np.random.Generator(np.random.PCG64(noise_seed if noise_seed is not None else 0))
+        noise = rng.normal(0.0, noise_sigma, size=rng_.shape)
+        valid = rng_ > 0
+        rng_ = np.where(valid, rng_ + noise, 0.0)
+        rng_ = np.where((rng_ > geom.r_min) & (rng_ <= geom.r_max), rng_, 0.0)
+    return rng_.astype(dtype)

@@ -234,6 +234,7 @@ typedef struct {
     int row0, row1;
     const int *bin_start, *bin_items;
     int nbins;
+    const double *Rcol, *ocol; /* per-column poses (a sweep taken while moving), or NULL */
 } job_t;
 
 static void *render_rows(void *arg) {
@@ -247,7 +248,9 @@ static void *render_rows(void *arg) {
             double az = 2.0 * M_PI * (double)j / (double)g->cols;
             double u[3] = {ce * cos(az), ce * sin(az), se};
             double d[3];
-            for (int a = 0; a < 3; a++) d[a] = R[3 * a] * u[0] + R[3 * a + 1] * u[1] + R[3 * a + 2] * u[2];
+            const double *Rj = jb->Rcol ? jb->Rcol + 9 * (size_t)j : R;
+            const double *oj = jb->ocol ? jb->ocol + 3 * (size_t)j : jb->o;
+            for (int a = 0; a < 3; a++) d[a] = Rj[3 * a] * u[0] + Rj[3 * a + 1] * u[1] + Rj[3 * a + 2] * u[2];
             hit_t h;
             h.t = INFINITY;
             h.id = 0;
@@ -262,7 +265,7 @@ static void *render_rows(void *arg) {
                 list = jb->bin_items + jb->bin_start[b];
                 ncand = jb->bin_start[b + 1] - jb->bin_start[b];
             }
-            cast(jb->sc, jb->o, d, &h, list, ncand);
+            cast(jb->sc, oj, d, &h, list, ncand);
             size_t px = (size_t)i * g->cols + j;
             int valid = isfinite(h.t) && h.t <= g->r_max;
             jb->range[px] = valid ? h.t : 0.0;
@@ -270,7 +273,7 @@ static void *render_rows(void *arg) {
                 for (int a = 0; a < 3; a++) {
                     /* sensor-frame normal = R^T n_world */
                     jb->normal[3 * px + a] =
-                        valid ? R[a] * h.n[0] + R[3 + a] * h.n[1] + R[6 + a] * h.n[2] : 0.0;
+                        valid ? Rj[a] * h.n[0] + Rj[3 + a] * h.n[1] + Rj[6 + a] * h.n[2] : 0.0;
                 }
             }
             if (jb->hit_id) jb->hit_id[px] = valid ? h.id : 0;
@@ -350,7 +353,7 @@ int syn_render(const syn_scene *sc, const syn_geom *g, const double *R, const do
         int r0 = k * per, r1 = r0 + per;
         if (r1 > g->rows) r1 = g->rows;
         if (r0 >= r1) break;
-        jobs[nj] = (job_t){sc, g, R, o, range, normal, hit_id, r0, r1, bs, bi, nbins};
+        jobs[nj] = (job_t){sc, g, R, o, range, normal, hit_id, r0, r1, bs, bi, nbins, NULL, NULL};
         nj++;
     }
     for (int k = 1; k < nj; k++) pthread_create(&th[k], NULL, render_rows, &jobs[k]);
@@ -360,3 +363,30 @@ int syn_render(const syn_scene *sc, const syn_geom *g, const double *R, const do
     free(bi);
     return 0;
 }
+
+/*
+ * Render a sweep taken while the sensor moves: column j is captured from its
+ * own pose (Rcol + 9 j world <- sensor, ocol + 3 j origin).  No azimuth bins
+ * (the origin changes from column to column): every cylinder is tested.
+ */
+int syn_render_sweep(const syn_scene *sc, const syn_geom *g, const double *Rcol, const double *ocol, double *range,
+                     int nthreads) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 64) nthreads = 64;
+    job_t jobs[64];
+    pthread_t th[64];
+    int per = (g->rows + nthreads - 1) / nthreads;
+    int nj = 0;
+    for (int k = 0; k < nthreads; k++) {
+        int r0 = k * per, r1 = r0 + per;
+        if (r1 > g->rows) r1 = g->rows;
+        if (r0 >= r1) break;
+        jobs[nj] = (job_t){sc, g, Rcol, ocol, range, NULL, NULL, r0, r1, NULL, NULL, 0, Rcol, ocol};
+        nj++;
+    }
+    for (int k = 1; k < nj; k++) pthread_create(&th[k], NULL, render_rows, &jobs[k]);
+    if (nj > 0) render_rows(&jobs[0]);
+    for (int k = 1; k < nj; k++) pthread_join(th[k], NULL);
+    return 0;
+}
+

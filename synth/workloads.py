@@ -12,7 +12,7 @@ import math
 
 import numpy as np
 
-from . import Geom, inv, lidar_geom, outdoor_scene, render, room_scene, rot_x, rot_y, rot_z, se3
+from . import Geom, inv, lidar_geom, outdoor_scene, render, render_sweep, room_scene, rot_x, rot_y, rot_z, se3
 
 DEG = math.pi / 180.0
 
@@ -252,3 +252,71 @@ def moving_objects_pair(seed: int, rows: int = 64, cols: int = 1024, n_movers: i
     mover_b = np.abs(render(scene_b, g, T_w_b, dtype=np.float64) - render(static, g, T_w_b, dtype=np.float64)) > 1e-9
     return dict(geom=g, kf_a=kf_a, kf_b=kf_b, T_ba=inv(T_w_b) @ T_w_a, T_world_a=T_w_a, T_world_b=T_w_b,
                 mover_a=mover_a, mover_b=mover_b, static=static, movers_a=mov_a, movers_b=mov_b)
+
+
+# ----------------------------------------------------------------------------
+# a closed loop through the outdoor scene (keyframe switching, loop closure)
+# ----------------------------------------------------------------------------
+
+def loop_sequence(seed: int = 5, n_scans: int = 64, radius: float = 10.0, rows: int = 64, cols: int = 1024,
+                  noise: float = 0.01, laps: float = 1.25, dtype=np.float32):
+    """``n_scans`` sweeps along a circle of ``radius`` metres through the
+    outdoor scene, ``laps`` times around (past the start again), heading along
+    the path with small seeded roll and pitch.  Returns dict(geom, scans
+    [list of ranges], T_world [list of 4x4], scene)."""
+    g = lidar_geom(rows, cols)
+    rng = np.random.Generator(np.random.PCG64(seed + 7877))
+    ang = np.linspace(0.0, 2 * math.pi * laps, n_scans)
+    path = np.stack([radius * np.cos(ang), radius * np.sin(ang)], axis=1)
+    ring = np.stack([radius * np.cos(np.linspace(0, 2 * math.pi, 73)),
+                     radius * np.sin(np.linspace(0, 2 * math.pi, 73))], axis=1)
+    scene = outdoor_scene(seed + 1, ring)
+    poses = []
+    for k in range(n_scans):
+        heading = ang[k] + math.pi / 2
+        R = rot_z(heading) @ rot_y(rng.uniform(-0.5, 0.5) * DEG) @ rot_x(rng.uniform(-0.5, 0.5) * DEG)
+        z = 1.8 + _ground_z(scene, path[k])
+        poses.append(se3(R, [path[k, 0], path[k, 1], z]))
+    scans = [render(scene, g, P, noise, seed * 1000 + k, dtype=dtype) for k, P in enumerate(poses)]
+    return dict(geom=g, scans=scans, T_world=poses, scene=scene)
+
+
+# ----------------------------------------------------------------------------
+# a sweep taken while the sensor moves (panorama formation, de-skew)
+# ----------------------------------------------------------------------------
+
+def _twist_exp(xi):
+    import scipy.linalg
+    M = np.zeros((4, 4))
+    w, v = xi[:3], xi[3:]
+    M[:3, :3] = [[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]
+    M[:3, 3] = v
+    return scipy.linalg.expm(M)
+
+
+def moving_sweep(seed: int = 3, rows: int = 64, cols: int = 1024, omega=(0.0, 0.0, math.radians(90.0)),
+                 velocity=(0.0, 0.0, 0.0), period: float = 0.1, t_ref: float = 1.0, noise: float = 0.0,
+                 outdoor: bool = False, dtype=np.float32):
+    """One sweep of ``period`` seconds whose column j fires at time
+    t_j = j / cols (fraction of the period) while the sensor turns at the body
+    rate ``omega`` (rad/s) and moves at ``velocity`` (m/s, body frame), both
+    constant.  The reference instant is t_ref (1: the end of the sweep).
+    Returns dict(geom, raw (the sweep as measured), ref (the panorama rendered
+    at the reference pose), col_T [cols, 4, 4] (column j's frame -> the
+    reference frame: Exp((t_j - t_ref) period xi)), T_world_ref, scene)."""
+    g = lidar_geom(rows, cols)
+    rng = np.random.Generator(np.random.PCG64(seed + 6151))
+    xi = np.concatenate([np.asarray(omega, float), np.asarray(velocity, float)])
+    if outdoor:
+        p = np.array([0.0, 0.0])
+        scene = outdoor_scene(seed + 1, np.stack([p, p + 1.0]))
+        T_ref = se3(rot_z(rng.uniform(-math.pi, math.pi)), [0.0, 0.0, 1.8 + float(scene.ground_height(p[None])[0])])
+    else:
+        pos = np.array([rng.uniform(-3, 3), rng.uniform(-1.5, 1.5), 1.5])
+        scene = room_scene(seed, sensor_positions=[pos])
+        T_ref = se3(rot_z(rng.uniform(-math.pi, math.pi)), pos)
+    col_T = np.stack([_twist_exp((j / cols - t_ref) * period * xi) for j in range(cols)])
+    raw = render_sweep(scene, g, T_ref[None] @ col_T, noise, seed * 2 + 1, dtype=dtype)
+    ref = render(scene, g, T_ref, noise, seed * 2 + 2, dtype=dtype)
+    return dict(geom=g, raw=raw, ref=ref, col_T=col_T, T_world_ref=T_ref, scene=scene, xi=xi, period=period,
+                t_ref=t_ref)
