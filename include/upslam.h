@@ -198,6 +198,24 @@ ups_status ups_fuse_scan(ups_context *ctx, const ups_geom *scan_g, const float *
                          const ups_geom *kf_g, float *kf_surfel_d, uint16_t *kf_count_d, const ups_pose *T_d,
                          const ups_fuse_params *p, void *stream);
 
+/* Panorama formation (Section III-A): the measurements of one sweep, each
+ * taken in the frame of its own firing instant, are moved into the frame of a
+ * single instant and projected into a panoramic image that keeps the nearest
+ * return per pixel.  A valid range r at (i, j) of raw_g (row = beam, column =
+ * firing) gives x = r u(i, j) and y = C_j x; y lands on its pixel of out_g
+ * when |y| is a valid range of out_g, and the smallest |y| wins (the smaller
+ * measurement index among equal FP32 ranges).
+ *   raw_range_d  device float [raw rows][raw cols], 0 = no return;
+ *   col_T_d      device float [raw cols][12]: C_j as R (row-major) then t,
+ *                column j's frame -> the reference frame (e.g. the
+ *                gyroscope's rotations, t = 0), or NULL for the identity;
+ *   depth_d      device float [out rows][out cols], written (0 = empty);
+ *                out_g may differ from raw_g (a wider keyframe field of view).
+ * Uses the context's fill scratch (out rows * cols <= max_pixels): calls on
+ * one context must not overlap in time.  Two kernels on `stream`. */
+ups_status ups_splat_sweep(ups_context *ctx, const ups_geom *raw_g, const float *raw_range_d, const float *col_T_d,
+                           const ups_geom *out_g, float *depth_d, void *stream);
+
 /* ---- keyframe management (Section III-C) -------------------------------- */
 
 /* Moving-object check between two keyframes, run when the current keyframe

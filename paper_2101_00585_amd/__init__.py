@@ -117,6 +117,7 @@ def load():
         "ups_batch_fallback_run": [_P, _P, _P, _P],
         "ups_batch_grid_search": [_P, _P, _P, _P, _P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
+        "ups_splat_sweep": [_P, _P, _P, _P, _P, _P, _P],
         "ups_keyframe_consistency": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_classify_loop_closures": [_P, ctypes.c_int32, _P, ctypes.c_double, _P, _P, _P],
         "ups_autotune": [_P, ctypes.c_char_p],
@@ -379,6 +380,29 @@ def fuse_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, kf_count
                               else _dev_ptr(kf_count, torch.uint16, "keyframe count"),
                               _dev_ptr(T_t, torch.float64, "pose"), ctypes.byref(p), _stream()))
     return kf_surfel, kf_count
+
+
+def splat_sweep(ctx: Context, raw_geom, raw, col_T=None, out_geom=None, out=None):
+    """Panorama of ``out_geom`` (default: the sweep's own geometry) from a
+    sweep's ranges ``raw`` (device float32 [rows, cols]); ``col_T``: per-column
+    transforms into the reference frame as a device float32 [cols, 12] tensor,
+    a host array [cols, 4, 4] / [cols, 12], or None for the identity."""
+    torch = _torch()
+    dev = raw.device
+    og = out_geom or raw_geom
+    if col_T is not None and not isinstance(col_T, torch.Tensor):
+        a = np.asarray(col_T, dtype=np.float64)
+        if a.ndim == 3:
+            a = np.concatenate([a[:, :3, :3].reshape(-1, 9), a[:, :3, 3]], axis=1)
+        col_T = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+    if out is None:
+        out = torch.empty((og.rows, og.cols), dtype=torch.float32, device=dev)
+    rg, oc = geom_c(raw_geom), geom_c(og)
+    _check(_LIB.ups_splat_sweep(ctx.handle, ctypes.byref(rg), _dev_ptr(raw, torch.float32, "raw ranges"),
+                                None if col_T is None else _dev_ptr(col_T, torch.float32, "column transforms"),
+                                ctypes.byref(oc), _dev_ptr(out, torch.float32, "depth"), _stream()))
+    out._keep = col_T
+    return out
 
 
 class ups_consistency_params(ctypes.Structure):
