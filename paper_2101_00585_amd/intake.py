@@ -2,8 +2,8 @@
 the measurements of one sweep into the frame of a single instant.
 
 A sweep fires its columns one after the other (column j at the fraction
-j / cols of the sweep period).  The paper rotates every measurement into the
-rotational frame of one instant using the gyroscope, on the CPU; these are
+j / cols of the sweep period).  The paper corrects the orientation of every
+measurement to a common instant from the gyroscope, on the CPU; these are
 those host computations -- from gyroscope samples (rotation only) or from a
 constant body twist (rotation and translation, e.g. the velocity of a motion
 prior).  The projection into the panorama runs on the GPU
