@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-proposal", action="store_true", help="skip the learned-proposal variants")
+    ap.add_argument("--no-keyframes", action="store_true",
+                    help="skip the panorama-formation / keyframe-management measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--precision", choices=["kahan", "f32", "f64"], default="kahan",
@@ -410,6 +412,117 @@ def run_irls(args, torch, ups, synth, ctx, items, pairs, stream, ms_register, la
             "status_counts": {ups.STATUS[st]: int(sum(r["status"] == st for r in res)) for st in ups.STATUS}}
 
 
+def run_keyframes(args, torch, ups, synth, W, stream):
+    """Panorama formation and keyframe management at sensor scale: the sweep
+    splat with de-skew transforms, the mutual moving-object check of two
+    keyframes, loop-closure classes of 256 results (each timed from a graph of
+    10 calls with HIP events), and the keyframe map over a closed loop of
+    sweeps (host-driven, ms per sweep)."""
+    from paper_2101_00585_amd import intake
+    from paper_2101_00585_amd.keyframes import GpuBackend, KeyframeMap, MapParams
+    dev = torch.device("cuda:0")
+    out = {}
+    reps = max(2, args.batch_steps)
+    # ---- splat: a 128x1024 outdoor sweep, turning 90 deg/s and moving 5 m/s
+    sw = W.moving_sweep(rows=128, cols=1024, outdoor=True, velocity=(5.0, 0.0, 0.0),
+                        omega=(0.05, -0.03, np.radians(83.7)))
+    g = sw["geom"]
+    ctx = ups.Context(0, max_pixels=128 * 2048, max_batch=16, max_batch_pixels=16 * 128 * 2048)
+    raw = torch.from_numpy(np.ascontiguousarray(sw["raw"], dtype=np.float32)).to(dev)
+    colT = torch.from_numpy(intake.pack(sw["col_T"])).to(dev)
+    depth = torch.empty((g.rows, g.cols), dtype=torch.float32, device=dev)
+
+    def splat10():
+        for _ in range(10):
+            ups.splat_sweep(ctx, g, raw, colT, out=depth)
+
+    us_splat = time_graph(torch, capture(torch, stream, splat10), stream, reps) * 1e3 / 10
+    nvalid = int((raw > 0).sum().item())
+    npix = g.rows * g.cols
+    splat_bytes = 4 * npix + 48 * g.cols + 16 * nvalid + 20 * npix
+    log(f"splat 128x1024 sweep: {us_splat:.2f} us, {splat_bytes / (us_splat * 1e-6) / 1e9:.0f} GB/s")
+    out["splat_128x1024"] = {
+        "workload": "one 128x1024 outdoor sweep of 0.1 s (83.7 deg/s yaw, 5 m/s) -> 128x1024 panorama, "
+                    "per-column de-skew transforms, nearest return per pixel",
+        "us_per_sweep": round(us_splat, 3), "measurements": nvalid,
+        "algorithmic_bytes": splat_bytes,
+        "achieved_GBs": round(splat_bytes / (us_splat * 1e-6) / 1e9, 1)}
+    # ---- mutual moving-object check of two 128x1024 keyframes
+    mo = W.moving_objects_pair(3, rows=128, cols=1024)
+    ka = ups.panorama_normals(ctx, mo["geom"], torch.from_numpy(mo["kf_a"]).to(dev))
+    kb = ups.panorama_normals(ctx, mo["geom"], torch.from_numpy(mo["kf_b"]).to(dev))
+    ca = torch.ones((128, 1024), dtype=torch.int16, device=dev)
+    cb = torch.ones((128, 1024), dtype=torch.int16, device=dev)
+    T_ba = ups.pose_tensor(mo["T_ba"], dev)
+    ma = torch.empty((128, 1024), dtype=torch.uint8, device=dev)
+    mb = torch.empty_like(ma)
+    rem = torch.empty(2, dtype=torch.int32, device=dev)
+    _, _, r0 = ups.keyframe_consistency(ctx, mo["geom"], ka, ca, mo["geom"], kb, cb, T_ba, a_mask=ma, b_mask=mb,
+                                        removed=rem)
+    removed = [int(v) for v in r0.cpu().numpy()]
+
+    def check10():
+        for _ in range(10):
+            ups.keyframe_consistency(ctx, mo["geom"], ka, ca, mo["geom"], kb, cb, T_ba, a_mask=ma, b_mask=mb,
+                                     removed=rem)
+
+    us_check = time_graph(torch, capture(torch, stream, check10), stream, reps) * 1e3 / 10
+    log(f"keyframe check 2 x 128x1024: {us_check:.2f} us, removed {removed}")
+    out["consistency_2x128x1024"] = {
+        "workload": "mutual moving-object check of two 128x1024 room keyframes 3 m apart with 3 + 3 movers",
+        "us_per_check": round(us_check, 3), "removed_first_call": removed}
+    # ---- loop-closure classes of 256 results
+    res = torch.zeros((256, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
+    cls = torch.empty(256, dtype=torch.int32, device=dev)
+    best = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def cls10():
+        for _ in range(10):
+            ups.load().ups_classify_loop_closures(ctx.handle, 256, ups._P(res.data_ptr()), 0.7,
+                                                  ups._P(cls.data_ptr()), ups._P(best.data_ptr()), ups._stream())
+
+    us_cls = time_graph(torch, capture(torch, stream, cls10), stream, reps) * 1e3 / 10
+    out["classify_256"] = {"us_per_call": round(us_cls, 3)}
+    ctx.close()
+    # ---- the keyframe map over a closed loop of 128x1024 sweeps
+    seq = W.loop_sequence(n_scans=64, radius=10.0, rows=128, cols=1024)
+    gq = seq["geom"]
+    ctx = ups.Context(0, max_pixels=gq.rows * gq.cols, max_batch=16, max_batch_pixels=16 * gq.rows * gq.cols)
+    depths = [torch.from_numpy(np.ascontiguousarray(d)).to(dev) for d in seq["scans"]]
+    m = KeyframeMap(GpuBackend(ctx, gq), MapParams(new_keyframe_ratio=0.75, search_radius=8.0))
+    torch.cuda.synchronize()
+    times, events, errs = [], [], []
+    P0 = seq["T_world"][0]
+    with torch.cuda.stream(stream):
+        for k, d in enumerate(depths):
+            t0 = time.perf_counter()
+            st = m.add_sweep(d)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+            events.append(st.event)
+            errs.append(synth.pose_error(st.T_world, np.linalg.inv(P0) @ seq["T_world"][k]))
+    ctx.close()
+    times = np.array(times)
+    ev = np.array(events)
+    errs = np.array(errs)
+    strong = sum(1 for e in m.edges if e.kind == "strong")
+    weak = sum(1 for e in m.edges if e.kind == "weak")
+    log(f"keyframe map: {len(depths)} sweeps, fused median {np.median(times[ev == 'fused']):.2f} ms, "
+        f"mean {times[1:].mean():.2f} ms, keyframes {len(m.keyframes)}, strong {strong}, weak {weak}")
+    out["keyframe_map_loop"] = {
+        "workload": "64 sweeps of 128x1024 along 1.25 laps of a 10 m circle (outdoor scene); fuse while the "
+                    "inlier ratio >= 0.75, else batched loop-closure search (grid search + registration + "
+                    "classes) over keyframes within 8 m, switch on a strong closure, new keyframe otherwise, "
+                    "mutual moving-object check at every switch; host-driven, one sync per sweep",
+        "ms_per_sweep_fused_median": round(float(np.median(times[ev == "fused"])), 3),
+        "ms_per_sweep_mean": round(float(times[1:].mean()), 3),
+        "ms_per_sweep_keyframe_change_median": round(float(np.median(times[1:][ev[1:] != "fused"])), 3),
+        "keyframes": len(m.keyframes), "strong_closures": strong, "weak_closures": weak,
+        "events": {e: int((ev == e).sum()) for e in ("fused", "new_keyframe", "switched")},
+        "max_pose_error_vs_truth_rad_m": [float(errs[:, 0].max()), float(errs[:, 1].max())]}
+    return out
+
+
 def _successes(res, pairs, synth):
     ok = []
     for r, p in zip(res, pairs):
@@ -606,6 +719,8 @@ def main():
         out["config"]["ms_per_128x1024_batched"] = out["batched"]["ms_per_128x1024_equivalent"]
         if "learned" in out["batched"]:
             out["config"]["ms_per_128x1024_batched_learned"] = out["batched"]["learned"]["ms_per_128x1024_equivalent"]
+    if not args.no_keyframes:
+        out["keyframes"] = run_keyframes(args, torch, ups, synth, W, stream)
     if not args.no_cpu_baseline:
         model, ncpu = cpu_info()
         log(f"cpu baseline (oracle, 1 thread) on {model}")
