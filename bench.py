@@ -50,8 +50,8 @@ HBM_PEAK_GBS = 8000.0
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
-TRAFFIC_KIB = {"single": (2519.17, 64.17), "batch": (498219.22, 983.0)}
-TRAFFIC_SRC_HASH = "0ca3551e6c84c740"
+TRAFFIC_KIB = {"single": (2519.17, 64.17), "batch": (498116.73, 983.0)}
+TRAFFIC_SRC_HASH = "3d7f906046cd5cfc"
 TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip", "ups_icp.hpp",
                "ups_device.hpp", "ups_internal.hpp")
 
@@ -246,6 +246,9 @@ def run_single(args, torch, ups, synth, W, stream):
     ms_per_step = elapsed / args.steps * 1e3
     px_it = sum(ITERS[l] * (g.rows >> l) * (g.cols >> l) for l in range(LEVELS))
     value = px_it / (ms_per_step / 1e3)
+    # pixel-iterations over scan pixels with a surfel (level l keeps every 2^l-th row and column)
+    ok = (scan_surf[..., 3] > 0) & (scan_surf[..., :3].abs().sum(-1) > 0)
+    valid_px_it = sum(res["level_iters"][l] * int(ok[::1 << l, ::1 << l].sum().item()) for l in range(LEVELS))
     log(f"single: {ms_per_step:.4f} ms/step, {value / 1e9:.3f} G px-it/s, pose vs truth {rot:.2e} rad {tr:.2e} m")
 
     # dominant kernel: the level-0 Gauss-Newton launch, timed as the
@@ -276,7 +279,7 @@ def run_single(args, torch, ups, synth, W, stream):
                 "note": "one 128x1024 registration: 4 MB per launch, cache-resident and latency bound"}
     ctx.close()
     return dict(c1=c1, value=value, ms_per_step=ms_per_step, px_it=px_it, rot=rot, tr=tr, res=res,
-                roofline=roofline)
+                roofline=roofline, valid_px_it=valid_px_it)
 
 
 # ----------------------------------------------------------------------------
@@ -710,6 +713,7 @@ def main():
         "config": {"workload": "plain single registration, 128x1024 outdoor scene, keyframe fused from 10 scans, "
                                "3-level pyramid 10/10/10 GN iterations + normals + fusion",
                    "pixel_iterations_per_step": single["px_it"],
+                   "valid_pixel_iterations_per_s": round(single["valid_px_it"] / (single["ms_per_step"] / 1e3), 1),
                    "ms_per_128x1024_registration": round(single["ms_per_step"], 5),
                    "pose_error_vs_truth_rad_m": [single["rot"], single["tr"]], "parallelism": "none (1 GPU)"},
         "roofline": single["roofline"],

@@ -463,6 +463,13 @@ void ups_proposal_destroy(ups_proposal *p);
  * Adam moments and step count. */
 ups_status ups_proposal_set_params(ups_proposal *p, const float *params_h, int64_t n);
 ups_status ups_proposal_get_params(ups_proposal *p, float *params_h, int64_t n);
+
+/* The parameters to / from a file: the 8 bytes "UPSPRM01", the parameter
+ * count (little-endian int64, ups_proposal_num_params()), then the FP32
+ * parameters.  load rejects any other content with UPS_ERR_INVALID_ARG and,
+ * like set_params, resets the Adam moments.  Synchronous. */
+ups_status ups_proposal_save(ups_proposal *p, const char *path);
+ups_status ups_proposal_load(ups_proposal *p, const char *path);
 /* Gradient of the last training step. */
 ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n);
 

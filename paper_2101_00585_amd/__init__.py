@@ -129,6 +129,8 @@ def load():
         "ups_proposal_set_params": [_P, _P, i64],
         "ups_proposal_get_params": [_P, _P, i64],
         "ups_proposal_get_grads": [_P, _P, i64],
+        "ups_proposal_save": [_P, ctypes.c_char_p],
+        "ups_proposal_load": [_P, ctypes.c_char_p],
         "ups_proposal_plan_input": [_P, i32, _P, _P],
         "ups_proposal_input": [_P, _P, _P],
         "ups_proposal_forward": [_P, i32, _P, _P, _P],
@@ -742,6 +744,7 @@ class Proposal:
         h = _P()
         _check(load().ups_proposal_create(ctx.handle, int(max_batch), ctypes.byref(h)))
         self._h = h
+        self.ctx = ctx
         self.max_batch = max_batch
         self.n_params = proposal_num_params()
         self._planned = None
@@ -756,6 +759,14 @@ class Proposal:
         a = np.empty(self.n_params, dtype=np.float32)
         _check(_LIB.ups_proposal_get_params(self._h, a.ctypes.data_as(_P), int(a.size)))
         return a
+
+    def save(self, path: str):
+        """Write the parameters to ``path`` (the library's parameter file)."""
+        _check(_LIB.ups_proposal_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        """Read parameters written by ``save`` (resets the Adam moments)."""
+        _check(_LIB.ups_proposal_load(self._h, os.fsencode(path)))
 
     def get_grads(self) -> np.ndarray:
         a = np.empty(self.n_params, dtype=np.float32)

@@ -3,7 +3,8 @@
 // preparation from range images and conversion of the output to poses.  The
 // network (five 3x3 BF16 convolutions with ReLU, then a 4096 -> 6 FP32 layer)
 // proposes the scan -> keyframe pose that starts a registration; plain
-// identity-started ICP remains the fallback (see ups_register_batch_masked).
+// identity-started ICP remains the fallback (ups_register_batch_fallback).
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -267,6 +268,42 @@ ups_status ups_proposal_get_params(ups_proposal *p, float *params_h, int64_t n) 
     UPS_CHECK_HIP(hipDeviceSynchronize());
     UPS_CHECK_HIP(hipMemcpy(params_h, p->params, n * sizeof(float), hipMemcpyDeviceToHost));
     return UPS_OK;
+}
+
+// Parameter file: the 8 bytes "UPSPRM01", the parameter count as a
+// little-endian int64, then the FP32 parameters in the layout's order.
+static const char kParamMagic[8] = {'U', 'P', 'S', 'P', 'R', 'M', '0', '1'};
+
+ups_status ups_proposal_save(ups_proposal *p, const char *path) {
+    UPS_REQUIRE(p && path, "null argument");
+    const int64_t n = layout().total;
+    std::vector<float> h(n);
+    ups_status st = ups_proposal_get_params(p, h.data(), n);
+    if (st != UPS_OK) return st;
+    FILE *f = fopen(path, "wb");
+    UPS_REQUIRE(f != nullptr, std::string("cannot open ") + path + " for writing");
+    const bool ok = fwrite(kParamMagic, 1, 8, f) == 8 && fwrite(&n, sizeof(n), 1, f) == 1 &&
+                    fwrite(h.data(), sizeof(float), n, f) == (size_t)n;
+    const bool closed = fclose(f) == 0;
+    UPS_REQUIRE(ok && closed, std::string("write to ") + path + " failed");
+    return UPS_OK;
+}
+
+ups_status ups_proposal_load(ups_proposal *p, const char *path) {
+    UPS_REQUIRE(p && path, "null argument");
+    const int64_t n = layout().total;
+    FILE *f = fopen(path, "rb");
+    UPS_REQUIRE(f != nullptr, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t m = -1;
+    std::vector<float> h(n);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kParamMagic, 8) == 0 && fread(&m, sizeof(m), 1, f) == 1 &&
+              m == n && fread(h.data(), sizeof(float), n, f) == (size_t)n;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    fclose(f);
+    UPS_REQUIRE(ok, std::string(path) + " is not a parameter file of this network");
+    return ups_proposal_set_params(p, h.data(), n);
 }
 
 ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n) {

@@ -222,3 +222,31 @@ def test_poses_from_outputs(gpu_lib, prop):
         T = C.proposal_pose(y[k].astype(np.float64))
         np.testing.assert_allclose(P[k, :9].reshape(3, 3), T[:3, :3], atol=1e-14)
         np.testing.assert_allclose(P[k, 9:], T[:3, 3], atol=1e-14)
+
+
+def test_parameter_file_round_trip(gpu_lib, prop, tmp_path):
+    """save / load through the C ABI: the same parameters come back in a new
+    network object; other files are rejected."""
+    path = str(tmp_path / "params.bin")
+    ref = prop.get_params()
+    prop.save(path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"UPSPRM01" and int.from_bytes(raw[8:16], "little") == ref.size
+    assert len(raw) == 16 + 4 * ref.size
+    other = gpu_lib.Proposal(prop.ctx, 4)
+    try:
+        other.load(path)
+        assert np.array_equal(other.get_params(), ref)
+        bad = tmp_path / "bad.bin"
+        bad.write_bytes(raw[:-4])              # truncated
+        with pytest.raises(gpu_lib.UpsError):
+            other.load(str(bad))
+        bad.write_bytes(b"XXXXXXXX" + raw[8:])  # wrong magic
+        with pytest.raises(gpu_lib.UpsError):
+            other.load(str(bad))
+        bad.write_bytes(raw + b"\0")           # trailing bytes
+        with pytest.raises(gpu_lib.UpsError):
+            other.load(str(bad))
+        assert np.array_equal(other.get_params(), ref)
+    finally:
+        other.close()
