@@ -50,9 +50,12 @@ def ctx(gpu_lib):
     c.close()
 
 
-def test_scores_match_oracle_counts(gpu_lib, ctx):
+# (n_yaw, n_xy): the per-yaw kernels (1 to 5 grid cells per axis, yaw chunks
+# that do not divide n_yaw included) and the general kernel (6 cells per axis)
+@pytest.mark.parametrize("n_yaw,n_xy", [(12, 3), (7, 1), (5, 2), (3, 4), (2, 5), (2, 6)])
+def test_scores_match_oracle_counts(gpu_lib, ctx, n_yaw, n_xy):
     pairs = [W.batch_pair(k, base_seed=5_000_000, max_angle=math.radians(90.0), size=(64, 512)) for k in range(2)]
-    gp = gpu_lib.GridParams(level=2, n_yaw=12, n_xy=3, xy_step=1.0, d_max=2.0)
+    gp = gpu_lib.GridParams(level=2, n_yaw=n_yaw, n_xy=n_xy, xy_step=0.7, d_max=2.0)
     items = _items(pairs)
     b = gpu_lib.Batch(ctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
     b.normals()
@@ -60,14 +63,15 @@ def test_scores_match_oracle_counts(gpu_lib, ctx):
     scores = scores.cpu().numpy()
     best = best.cpu().numpy()
     best_score = best_score.cpu().numpy()
-    C = 12 * 9
+    C = n_yaw * n_xy * n_xy
+    assert scores.shape == (len(pairs), C)
     for k, p in enumerate(pairs):
         g = p["geom"]
         gl = g.level(2)
         sl = O.pyramid_level(g, O.panorama_normals(g, p["scan"]), 2)
         kl = O.pyramid_level(g, O.panorama_normals(g, p["kf"]), 2)
         valid = int((sl[..., 3] > 0).sum())
-        ref = np.array([int(O.correspondences(gl, sl, gl, kl, _candidate(c, 12, 3, 1.0), 2.0,
+        ref = np.array([int(O.correspondences(gl, sl, gl, kl, _candidate(c, n_yaw, n_xy, 0.7), 2.0,
                                               math.cos(math.radians(30.0)))[1].sum()) for c in range(C)])
         tol = max(2, int(0.01 * valid))
         assert np.abs(scores[k] - ref).max() <= tol, (k, np.abs(scores[k] - ref).max(), tol)
@@ -77,7 +81,7 @@ def test_scores_match_oracle_counts(gpu_lib, ctx):
         T = np.eye(4)
         T[:3, :3] = best[k, :9].reshape(3, 3)
         T[:3, 3] = best[k, 9:]
-        np.testing.assert_allclose(T, _candidate(c_best, 12, 3, 1.0), atol=1e-12)
+        np.testing.assert_allclose(T, _candidate(c_best, n_yaw, n_xy, 0.7), atol=1e-12)
     b.close()
 
 
@@ -131,4 +135,33 @@ def test_grid_search_replays_from_a_graph(gpu_lib, ctx):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(scores.cpu().numpy(), eager[0]) and np.array_equal(best.cpu().numpy(), eager[1])
+    b.close()
+
+
+def test_scores_around_a_base_pose(gpu_lib, ctx):
+    """The candidates are base * G_c: scores against the oracle's counts at
+    base * G_c for a base pose per registration."""
+    import torch
+    pairs = [W.batch_pair(k, base_seed=5_100_000, max_angle=math.radians(40.0), size=(64, 512)) for k in range(2)]
+    bases = [synth.se3(synth.rot_z(0.3 + k), [0.5, -0.2 * k, 0.05]) for k in range(2)]
+    gp = gpu_lib.GridParams(level=2, n_yaw=4, n_xy=3, xy_step=0.5, d_max=2.0)
+    b = gpu_lib.Batch(ctx, _items(pairs), gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.normals()
+    base_t = torch.stack([gpu_lib.pose_tensor(T) for T in bases])
+    best, _, scores = b.grid_search(gp, base_t)
+    scores = scores.cpu().numpy()
+    for k, p in enumerate(pairs):
+        g = p["geom"]
+        gl = g.level(2)
+        sl = O.pyramid_level(g, O.panorama_normals(g, p["scan"]), 2)
+        kl = O.pyramid_level(g, O.panorama_normals(g, p["kf"]), 2)
+        ref = np.array([int(O.correspondences(gl, sl, gl, kl, bases[k] @ _candidate(c, 4, 3, 0.5), 2.0,
+                                              math.cos(math.radians(30.0)))[1].sum()) for c in range(36)])
+        tol = max(2, int(0.01 * int((sl[..., 3] > 0).sum())))
+        assert np.abs(scores[k] - ref).max() <= tol
+        c_best = int(np.argmax(scores[k]))
+        T = np.eye(4)
+        T[:3, :3] = best.cpu().numpy()[k, :9].reshape(3, 3)
+        T[:3, 3] = best.cpu().numpy()[k, 9:]
+        np.testing.assert_allclose(T, bases[k] @ _candidate(c_best, 4, 3, 0.5), atol=1e-12)
     b.close()

@@ -153,3 +153,25 @@ def test_loop_closure_classes_match_oracle(gpu_lib, ctx, n):
     ref_cls, ref_best = O.loop_closure_classes(ratios, statuses, 0.5)
     assert np.array_equal(_np(cls), ref_cls)
     assert int(_np(best)[0]) == ref_best
+
+
+def test_keyframes_of_different_geometries(gpu_lib, ctx):
+    """A 64x1024 sweep-sized keyframe checked against a 128x2048 one (wider
+    field of view), both directions, against the oracle."""
+    import torch
+    c = W.moving_objects_pair(2, rows=64, cols=1024)
+    gb = lidar_geom(128, 2048)
+    import synth
+    sc_b = type(c["static"])(room=c["static"].room, boxes=np.vstack([c["static"].boxes, c["movers_b"]]), kind="room")
+    kb_depth = synth.render(sc_b, gb, c["T_world_b"], 0.01, 77)
+    a = O.panorama_normals(c["geom"], c["kf_a"]).astype(np.float32)
+    b = O.panorama_normals(gb, kb_depth).astype(np.float32)
+    _, _, _, _, ma_ref, mb_ref = O.keyframe_consistency(c["geom"], a, None, gb, b, None, c["T_ba"])
+    ma, mb, removed = gpu_lib.keyframe_consistency(ctx, c["geom"], _t(a), None, gb, _t(b), None, c["T_ba"])
+    torch.cuda.synchronize()
+    ma, mb = _np(ma).astype(bool), _np(mb).astype(bool)
+    flips = int((ma != ma_ref).sum() + (mb != mb_ref).sum())
+    print(f"64x1024 vs 128x2048: removed A {ma.sum()} (oracle {ma_ref.sum()}), B {mb.sum()} (oracle {mb_ref.sum()}), "
+          f"flips {flips}")
+    assert ma_ref.sum() > 0 and mb_ref.sum() > 0
+    assert flips <= 5e-4 * (ma.size + mb.size)
