@@ -131,19 +131,6 @@ def augment_inputs(x, k, flip, k2=None):
 
 # ---------------------------------------------------------------- data
 
-def render_pairs(n, base_seed, max_angle_deg=30.0, max_trans=2.0, sizes=((64, 512), (128, 1024)), log=None):
-    """Rendered pairs (scene kind, size and motion seeded by base_seed + k)."""
-    from synth import workloads as W
-    out = []
-    t0 = time.perf_counter()
-    for k in range(n):
-        out.append(W.batch_pair(k, base_seed=base_seed, max_angle=math.radians(max_angle_deg),
-                                max_trans=max_trans, sizes=sizes))
-        if log and (k + 1) % 500 == 0:
-            log(f"rendered {k + 1}/{n} pairs ({time.perf_counter() - t0:.0f} s)")
-    return out
-
-
 def _pair_items(pairs, dev):
     torch = _torch()
     items = []
@@ -187,6 +174,40 @@ def build_dataset(ctx, prop, pairs, chunk=256, log=None):
         if log:
             log(f"labelled {min(c0 + chunk, len(pairs))}/{len(pairs)} pairs")
     return torch.cat(xs), np.array(ys), np.array(keep)
+
+
+def _render_chunk(job):
+    """Training pairs c0..c1-1 (seeds base_seed + k): yaw up to 30 deg,
+    translation up to 2 m, 64x512 or 128x1024."""
+    c0, c1, base_seed = job
+    from synth import workloads as W
+    return [W.batch_pair(k, base_seed=base_seed, max_angle=math.radians(30.0), max_trans=2.0,
+                         sizes=((64, 512), (128, 1024))) for k in range(c0, c1)]
+
+
+def _render_worker_init():
+    import synth
+    synth.DEFAULT_THREADS = 1  # one ray-casting thread per worker process
+
+
+def labelled_inputs(ctx, prop, n, base_seed, chunk=256, log=None, pool=None):
+    """build_dataset over n pairs rendered chunk by chunk (only the 32x256
+    network inputs and the labels are kept, so the full-resolution renders
+    of a large training set never sit in memory together).  pool: a process
+    pool (created before the GPU is touched) that renders chunks ahead."""
+    torch = _torch()
+    xs, ys, keeps = [], [], []
+    t0 = time.perf_counter()
+    jobs = [(c0, min(n, c0 + chunk), base_seed) for c0 in range(0, n, chunk)]
+    chunks = pool.imap(_render_chunk, jobs) if pool is not None else map(_render_chunk, jobs)
+    for (c0, _, _), pairs in zip(jobs, chunks):
+        x, y, keep = build_dataset(ctx, prop, pairs, chunk=chunk)
+        xs.append(x)
+        ys.append(y)
+        keeps.append(keep)
+        if log and (c0 // chunk) % 20 == 19:
+            log(f"rendered and labelled {min(n, c0 + chunk)}/{n} pairs ({time.perf_counter() - t0:.0f} s)")
+    return torch.cat(xs), np.concatenate(ys), np.concatenate(keeps)
 
 
 def init_params(seed=0):
@@ -362,20 +383,28 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=PARAMS_FILE)
     ap.add_argument("--log-json", default=None)
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes that render training pairs")
     a = ap.parse_args(argv)
-    torch = _torch()
 
     def log(m):
         print(f"[train] {m}", file=sys.stderr, flush=True)
 
+    # the rendering workers are forked before anything touches the GPU
+    pool = None
+    if a.workers > 1:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(a.workers, initializer=_render_worker_init)
+    torch = _torch()
     load()
-    log(f"rendering {a.pairs} training pairs and {a.val_pairs} validation pairs")
-    train_pairs = render_pairs(a.pairs, 1_000_000, log=log)
-    val_pairs = render_pairs(a.val_pairs, 3_000_000, log=log)
+    log(f"rendering and labelling {a.pairs} training pairs and {a.val_pairs} validation pairs")
     ctx = Context(0, max_pixels=128 * 2048, max_batch=256, max_batch_pixels=256 * 128 * 2048)
     prop = Proposal(ctx, max(a.batch, 256))
-    x, y, keep = build_dataset(ctx, prop, train_pairs, log=log)
-    xv, yv, kv = build_dataset(ctx, prop, val_pairs, log=log)
+    x, y, keep = labelled_inputs(ctx, prop, a.pairs, 1_000_000, log=log, pool=pool)
+    xv, yv, kv = labelled_inputs(ctx, prop, a.val_pairs, 3_000_000, log=log, pool=pool)
+    if pool is not None:
+        pool.close()
+        pool.join()
     kt = torch.from_numpy(keep).to(x.device)
     x, y = x[kt].contiguous(), y[keep]
     xv, yv = xv[torch.from_numpy(kv).to(xv.device)].contiguous(), yv[kv]

@@ -30,6 +30,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 
+# ray-casting threads per render when the caller gives none (None: up to 16);
+# worker processes that render in parallel set it to 1
+DEFAULT_THREADS = None
+
+
 def _lib():
     global _LIB
     if _LIB is None:
@@ -286,7 +291,7 @@ def render(scene: Scene, geom: Geom, T_world_sensor, noise_sigma: float = 0.0, n
     sc, keep = scene._c()
     g = _GeomC(geom.rows, geom.cols, geom.el_top, geom.d_el, geom.r_max)
     if threads is None:
-        threads = min(16, os.cpu_count() or 1)
+        threads = DEFAULT_THREADS or min(16, os.cpu_count() or 1)
     _lib().syn_render(ctypes.byref(sc), ctypes.byref(g), R.ctypes.data_as(ctypes.c_void_p),
                       o.ctypes.data_as(ctypes.c_void_p), rng_.ctypes.data_as(ctypes.c_void_p),
                       nrm.ctypes.data_as(ctypes.c_void_p) if nrm is not None else None, None,
@@ -318,7 +323,7 @@ def render_sweep(scene: Scene, geom: Geom, T_world_cols, noise_sigma: float = 0.
     sc, keep = scene._c()
     g = _GeomC(geom.rows, geom.cols, geom.el_top, geom.d_el, geom.r_max)
     if threads is None:
-        threads = min(16, os.cpu_count() or 1)
+        threads = DEFAULT_THREADS or min(16, os.cpu_count() or 1)
     _lib().syn_render_sweep(ctypes.byref(sc), ctypes.byref(g), R.ctypes.data_as(ctypes.c_void_p),
                             o.ctypes.data_as(ctypes.c_void_p), rng_.ctypes.data_as(ctypes.c_void_p),
                             ctypes.c_int(threads))
