@@ -120,7 +120,7 @@ ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels,
     c->max_batch = max_batch;
     c->max_batch_pixels = max_batch_pixels;
     const int64_t pyr = (max_pixels * 21 + 63) / 64 + 64;
-    c->max_partial_blocks = max_pixels / kBlock + 64;  // single registrations (batches own theirs)
+    c->max_partial_blocks = partial_stride(max_pixels / kBlock + 64);  // single registrations (batches own theirs)
     c->lut_capacity = (size_t)1 << 20;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&c->pyr_scan, pyr * sizeof(float4));

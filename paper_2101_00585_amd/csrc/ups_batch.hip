@@ -29,7 +29,7 @@ struct ups_batch {
     int *d_pre_start = nullptr;   // [n+1]
     float4 *pyr = nullptr;
     RegState *state = nullptr;    // [n][2]
-    double *partials = nullptr;   // [n][2][pstride][kPartialStride]
+    double *partials = nullptr;   // [n][2][kPartialStride][pstride]
     // batched normals
     NormImg *d_nimg = nullptr;
     int *d_ntile_start = nullptr;
@@ -191,6 +191,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->d_pre_start, pre_start.size() * sizeof(int));
     alloc((void **)&b->pyr, std::max<int64_t>(pyr_total, 1) * sizeof(float4));
     alloc((void **)&b->state, (size_t)n * 2 * sizeof(RegState));
+    pstride = (int)partial_stride(pstride);
     alloc((void **)&b->partials, (size_t)n * 2 * pstride * kPartialStride * sizeof(double));
     alloc((void **)&b->ident, (size_t)n * sizeof(ups_pose));
     alloc((void **)&b->mask, (size_t)n);

@@ -12,8 +12,11 @@
 //      point-to-plane residual r = (q - s1).n1 and J = [q x n1, n1];
 //   2. the 29-value reduction [21 x J^T J | 6 x J^T r | r^2 | inliers]:
 //      Kahan-compensated FP32 per thread, then FP64 (or plain FP32 in the
-//      FP32 precision mode) DPP row sums and a fixed-order LDS sum per block,
-//      written as one partial per block.
+//      FP32 precision mode) quad sums by DPP and the 64 quad sums of each
+//      value added through LDS by 8 threads in a fixed order, written as one
+//      partial per block.  Partials are stored by value (value v of every
+//      block in one row), so that step 0 reads them with coalesced 16-byte
+//      loads, 8 threads per value, and issues the state load beside them.
 //
 // The registration state (pose, status, flags) lives in two ping-pong slots:
 // launch n reads slot n%2 and block 0 writes slot (n+1)%2.  Block partials are

@@ -27,8 +27,8 @@ struct Inst {
     DGeom sg[4], kg[4];           // geometry of each pyramid level
     const float4 *scan[4], *kf[4];  // surfel images of each level (level 0 = caller's)
     RegState *state;              // [2]
-    double *partials;             // [2][pstride][kPartialStride]
-    int pstride;
+    double *partials;             // [2][kPartialStride][pstride]: value v of block b at [v * pstride + b]
+    int pstride;                  // a multiple of 16
     int nblocks[4];               // blocks (tiles) per level
     ups_icp_result *res;          // finish target (or null)
     ups_normal_eq *neq;           // finish target (or null)

@@ -24,21 +24,27 @@ __device__ __forceinline__ double dpp_d(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over each 16-lane row (quad xor 1, quad xor 2, half-row mirror, row
-// mirror); every lane of a row ends with the bitwise-same row sum.
+// Sums over lane groups by DPP: quad_sum over each quad (xor 1, xor 2),
+// oct_sum over each group of 8 lanes (then the half-row mirror).  Every lane
+// of a group ends with the bitwise-same sum (the two operands of each
+// addition are the same pair in every lane, and addition commutes).
 template <typename T>
-__device__ __forceinline__ T row_sum(T v) {
+__device__ __forceinline__ T quad_sum(T v) {
     if constexpr (sizeof(T) == 8) {
         v += dpp_d<0xB1>(v);
         v += dpp_d<0x4E>(v);
-        v += dpp_d<0x141>(v);
-        v += dpp_d<0x140>(v);
     } else {
         v += dpp_f<0xB1>(v);
         v += dpp_f<0x4E>(v);
-        v += dpp_f<0x141>(v);
-        v += dpp_f<0x140>(v);
     }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T oct_sum(T v) {
+    v = quad_sum<T>(v);
+    if constexpr (sizeof(T) == 8) v += dpp_d<0x141>(v);
+    else v += dpp_f<0x141>(v);
     return v;
 }
 
@@ -158,48 +164,90 @@ __device__ __forceinline__ void add_terms(ThreadAcc<PREC, NV> &acc, const Pair &
     acc.count(28);
 }
 
-// Sum NV per-thread values over the 256-thread block in a fixed order: DPP row
-// sums, then the 16 row sums of each value added in row order.  tot[v] holds
-// the block total of value v for every thread after the call.
+// The block's sum of NV per-thread values, written as this block's partial
+// (value v at part_out[v * pstride + tile]), in a fixed order: quad sums by
+// DPP, the 64 quad sums of each value through LDS, then 8 threads per value
+// (thread g adds quads g, g+8, ..., g+56) and oct_sum.
 template <int NV, typename Acc>
-__device__ __forceinline__ void block_reduce(Acc (&x)[NV], Acc (*rows)[16], Acc *tot) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ __forceinline__ void block_partial(const Acc (&x)[NV], Acc (*qbuf)[65], double *part_out, int pstride,
+                                              int tile) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        const Acc y = row_sum<Acc>(x[v]);
-        if ((lane & 15) == 0) rows[v][wave * 4 + (lane >> 4)] = y;
+        const Acc y = quad_sum<Acc>(x[v]);
+        if ((tid & 3) == 0) qbuf[v][tid >> 2] = y;
     }
     __syncthreads();
-    if (tid < NV) {
-        Acc t = 0;
+    const int v = min(tid >> 3, NV - 1), g = tid & 7;
+    Acc t = 0;
 #pragma unroll
-        for (int r = 0; r < 16; r++) t += rows[tid][r];
-        tot[tid] = t;
+    for (int k = 0; k < 8; k++) t += qbuf[v][g + 8 * k];
+    t = oct_sum<Acc>(t);
+    if (g == 0 && (tid >> 3) < NV) part_out[(size_t)v * pstride + tile] = (double)t;
+}
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// Value v = tid / 8 (clamped to NV - 1) summed over the first n block
+// partials by the 8 threads of a group: thread g adds blocks 2g, 2g+1, 2g+16,
+// 2g+17, ... in that order (two blocks per 16-byte load, up to 16 loads in
+// flight), then oct_sum.  Every thread of the group returns the same total,
+// and every block that reads the same partials computes the same totals.
+template <int NV, typename Acc>
+__device__ __forceinline__ Acc sum_partials(const double *part, int pstride, int n) {
+    const int v = min((int)(threadIdx.x >> 3), NV - 1), g = threadIdx.x & 7;
+    const UPS_AS_GLOBAL double *pv = (const UPS_AS_GLOBAL double *)part + (size_t)v * pstride;
+    Acc t = 0;
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        const int nk = min(16, (n - b0 + 15) >> 4);  // block-uniform
+        v2d x[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            // an index past the last partial is clamped into the row and its value unused
+            x[k] = (v2d){0.0, 0.0};
+            if (k < nk) x[k] = *(const UPS_AS_GLOBAL v2d *)(pv + min(b0 + 16 * k + 2 * g, pstride - 2));
+        }
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const int b = b0 + 16 * k + 2 * g;
+            if (k < nk) {
+                t += (b < n) ? (Acc)x[k].x : Acc(0);
+                t += (b + 1 < n) ? (Acc)x[k].y : Acc(0);
+            }
+        }
     }
+    return oct_sum<Acc>(t);
+}
+
+// The totals of the first n partials into tot[0 .. NV-1] (LDS), visible to
+// the whole block on return.
+template <int NV, typename Acc>
+__device__ __forceinline__ void reduce_partials(const double *part, int pstride, int n, Acc *tot) {
+    const Acc t = sum_partials<NV, Acc>(part, pstride, n);
+    if ((threadIdx.x & 7) == 0 && (threadIdx.x >> 3) < NV) tot[threadIdx.x >> 3] = t;
     __syncthreads();
-}
-
-// Load this thread's share of `n` block partials (partials t, t+256, ... for
-// thread t) and add them up in that fixed order; block_reduce finishes.
-template <int NV, typename Acc>
-__device__ __forceinline__ void load_partials(const double *part, int n, Acc (&x)[NV]) {
-#pragma unroll
-    for (int v = 0; v < NV; v++) x[v] = 0;
-    for (int b = threadIdx.x; b < n; b += kBlock) {
-        const double *pb = part + (size_t)b * kPartialStride;
-#pragma unroll
-        for (int v = 0; v < NV; v++) x[v] += (Acc)pb[v];
-    }
-}
-
-template <int NV, typename Acc>
-__device__ __forceinline__ void reduce_partials(const double *part, int n, Acc (*rows)[16], Acc *tot) {
-    Acc x[NV];
-    load_partials<NV, Acc>(part, n, x);
-    block_reduce<NV, Acc>(x, rows, tot);
 }
 
 // --------------------------------------------------------- FP64 / FP32 solve
+
+// 1 / sqrt(d) for d > 0 (normal range): in FP64 the hardware estimate
+// refined by two Newton steps y <- y + y (1 - d y^2) / 2, each of which about
+// squares the relative error (e -> 1.5 e^2: an estimate good to 2^-14 already
+// ends at FP64 rounding); in FP32 the plain quotient.
+template <typename T>
+__device__ __forceinline__ T inv_sqrt(T d) {
+    if constexpr (sizeof(T) == 8) {
+        double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+            const double e = fma(-d * y, y, 1.0);
+            y = fma(0.5 * y, e, y);
+        }
+        return y;
+    } else {
+        return T(1) / sqrt(d);
+    }
+}
 
 template <typename T>
 __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
@@ -218,8 +266,7 @@ __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
         T d = A[c][c];
         for (int k = 0; k < c; k++) d -= L[c][k] * L[c][k];
         if (!(d > T(1e-12) * maxd)) return UPS_DEGENERATE;
-        L[c][c] = sqrt(d);
-        inv[c] = T(1) / L[c][c];
+        inv[c] = inv_sqrt<T>(d);  // 1 / L[c][c]
         for (int r = c + 1; r < 6; r++) {
             T s = A[r][c];
             for (int k = 0; k < c; k++) s -= L[r][k] * L[c][k];
@@ -248,9 +295,9 @@ __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
 template <typename T>
 __device__ void exp_compose(const T *xi, double *R, double *t) {
     const T w0 = xi[0], w1 = xi[1], w2 = xi[2];
-    const T th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    const T th2 = w0 * w0 + w1 * w1 + w2 * w2;
     T A, B, C;
-    if (th < T(0.25)) {
+    if (th2 < T(0.0625)) {
         // 1/n! for n = 1..17
         constexpr double f[18] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040,
                                   1.0 / 40320, 1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600,
@@ -264,6 +311,7 @@ __device__ void exp_compose(const T *xi, double *R, double *t) {
             C = C * th2 + sg * (T)f[2 * k + 3];
         }
     } else {
+        const T th = sqrt(th2);
         A = sin(th) / th;
         B = (T(1) - cos(th)) / th2;
         C = (th - sin(th)) / (th2 * th);
@@ -336,7 +384,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     double *part_out = I.partials + (size_t)(FUSED ? (a.parity ^ 1) : 0) * I.pstride * kPartialStride;
 
     __shared__ RegState S;
-    __shared__ Acc rows[31][16];
+    __shared__ Acc qbuf[31][65];
     __shared__ Acc tot[32];
     __shared__ int active;
     const DGeom sg = I.sg[l], kg = I.kg[l];
@@ -345,32 +393,46 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     const int npix = sg.rows * sg.cols;
     const int base = tile * (kBlock * K);
 
-    // ---- issue the independent loads together: the first scan surfel and
-    // its ray-table column, the previous launch's block partials and the state.
-    // Scan loads are clamped into the image (the last wavefronts of a tile may
-    // run past it) and masked afterwards, so no load sits behind a branch.
+    // ---- issue the independent loads together: the first pair of scan
+    // surfels and their ray-table columns, the previous launch's block
+    // partials and the state.  Scan loads are clamped into the image (the last
+    // wavefronts of a tile may run past it) and masked afterwards, so no load
+    // sits behind a branch.  Pixels go in pairs: both pixels' keyframe gathers
+    // are in flight before the first of them is consumed, and the next pair's
+    // scan loads behind them.
+    constexpr int P = (K >= 2) ? 2 : 1;
     const int pw0 = __builtin_amdgcn_readfirstlane(base + (tid & ~63));
     // column of this thread's pixel; it advances by kBlock mod cols per pixel
     const int col_step = kBlock % sg.cols;
-    int jn = (base + tid) % sg.cols;
-    float4 nxt = ldg_u(scan, (uint32_t)min(base + tid, npix - 1));
-    float2 nxt_a = ldg_u(sg.lut_col, (uint32_t)jn << sg.lshift);
+    float4 nx[P];
+    float2 na[P];
+    int jc[P];
+#pragma unroll
+    for (int u = 0; u < P; u++) {
+        if (u == 0) jc[u] = (base + tid) % sg.cols;
+        else jc[u] = jc[u - 1] + col_step >= sg.cols ? jc[u - 1] + col_step - sg.cols : jc[u - 1] + col_step;
+        nx[u] = ldg_u(scan, (uint32_t)min(base + u * kBlock + tid, npix - 1));
+        na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
+    }
     if (!FUSED) {
         if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
         if (MODE == MODE_EVAL && slot_in->skip) return;
         if (tid == 0) S = *slot_in;
         __syncthreads();
     } else {
-        Acc px[29];
-        load_partials<29, Acc>(part_in, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0, px);
-        if (tid == 0) S = *slot_in;
+        // the state, one 32-bit word per thread, loaded alongside the partials
+        constexpr int kStateWords = (int)(sizeof(RegState) / 4);
+        static_assert(sizeof(RegState) % 4 == 0 && kStateWords <= kBlock, "state copy");
+        uint32_t sword = 0;
+        if (tid < kStateWords) sword = ((const UPS_AS_GLOBAL uint32_t *)slot_in)[tid];
+        const Acc ptot =
+            sum_partials<29, Acc>(part_in, I.pstride, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0);
+        if (tid < kStateWords) ((uint32_t *)&S)[tid] = sword;
+        if ((tid & 7) == 0 && (tid >> 3) < 29) tot[tid >> 3] = ptot;
         __syncthreads();
         // ---- 0. the previous launch's update, solved identically by every block
-        if (S.pending && !S.stop) {
-            block_reduce<29, Acc>(px, rows, tot);
-            if (tid == 0) gn_step<Acc>(a, tot, S);
-        }
         if (tid == 0) {
+            if (S.pending && !S.stop) gn_step<Acc>(a, tot, S);
             S.pending = 0;
             if (MODE == MODE_ITER && a.first_of_level) S.level_active = 1;
             if (MODE == MODE_EVAL && a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
@@ -399,22 +461,6 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     }
     ThreadAcc<PREC, NV> acc;
     acc.zero();
-    // pixels in pairs: both pixels' keyframe gathers are in flight before the
-    // first of them is consumed, and the next pair's scan loads behind them
-    constexpr int P = (K >= 2) ? 2 : 1;
-    float4 nx[P];
-    float2 na[P];
-    int jc[P];
-    nx[0] = nxt;
-    na[0] = nxt_a;
-    jc[0] = jn;
-#pragma unroll
-    for (int u = 1; u < P; u++) {
-        jc[u] = jc[u - 1] + col_step;
-        jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-        nx[u] = ldg_u(scan, (uint32_t)min(base + u * kBlock + tid, npix - 1));
-        na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
-    }
     int pw = pw0;
     // groups of up to 4 pixels (the Kahan group), two unrolled per trip so
     // that the compensated sums need no register copies between trips
@@ -489,9 +535,8 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
         Acc x[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
-        block_reduce<NV, Acc>(x, rows, tot);
+        block_partial<NV, Acc>(x, qbuf, part_out, I.pstride, tile);
     }
-    if (tid < NV) part_out[(size_t)tile * kPartialStride + tid] = (double)tot[tid];
     if (FUSED && tile == 0 && tid == 0) {
         S.pending = (MODE == MODE_ITER);
         S.npartials = ntiles;
@@ -548,12 +593,11 @@ template <int PREC>
 __device__ __forceinline__ void solve_block(const Inst &I, const StepArgs &a) {
     using Acc = AccOf<PREC>;
     __shared__ RegState S;
-    __shared__ Acc rows[29][16];
     __shared__ Acc tot[32];
     if (threadIdx.x == 0) S = I.state[0];
     __syncthreads();
     if (S.active && !S.stop) {
-        reduce_partials<29, Acc>(I.partials, npartials_of(I.nblocks[a.prev_level]), rows, tot);
+        reduce_partials<29, Acc>(I.partials, I.pstride, npartials_of(I.nblocks[a.prev_level]), tot);
         if (threadIdx.x == 0) gn_step<Acc>(a, tot, S);
     }
     if (threadIdx.x == 0) {
@@ -585,12 +629,11 @@ __global__ __launch_bounds__(kBlock) void k_solve_batch_list(const Inst *__restr
 template <int PREC>
 __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_result *res, ups_normal_eq *neq) {
     using Acc = AccOf<PREC>;
-    __shared__ Acc rows[31][16];
     __shared__ Acc tot[32];
     const RegState *S = I.state + parity;
     if (S->skip) return;  // masked out of this batch call: the result is left as it was
-    reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, npartials_of(I.nblocks[0]),
-                             rows, tot);
+    reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, I.pstride,
+                             npartials_of(I.nblocks[0]), tot);
     if (threadIdx.x != 0) return;
     const double n_in = (double)tot[28], n_valid = (double)tot[29];
     if (res) {
@@ -645,13 +688,13 @@ __global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict_
 template <int PREC, int NV>
 __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
     using Acc = AccOf<PREC>;
-    __shared__ Acc rows[NV][16];
-    __shared__ Acc tot[32];
     RegState *S = I.state + parity;
     double *part = I.partials + (size_t)parity * I.pstride * kPartialStride;
     if (NV == 29 && !S->pending) return;
-    reduce_partials<NV, Acc>(part, S->npartials, rows, tot);
-    if (threadIdx.x < NV) part[threadIdx.x] = (double)tot[threadIdx.x];
+    // the 8 threads of value v read only row v, and have read all of it
+    // before the group's sum exists: the total can overwrite block 0's entry
+    const Acc t = sum_partials<NV, Acc>(part, I.pstride, S->npartials);
+    if ((threadIdx.x & 7) == 0 && (threadIdx.x >> 3) < NV) part[(size_t)(threadIdx.x >> 3) * I.pstride] = (double)t;
     __syncthreads();
     if (threadIdx.x == 0) S->npartials = 1;
 }

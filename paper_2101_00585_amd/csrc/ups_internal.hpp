@@ -55,7 +55,7 @@ struct ups_context {
     float4 *pyr_kf = nullptr;
     float4 *tmp_surfel = nullptr;  // a-trous ping-pong, max_pixels
     unsigned long long *fill_key = nullptr;  // fuse fill pass, max_pixels
-    double *partials = nullptr;              // [2][max_partial_blocks][kPartialStride] block partials
+    double *partials = nullptr;              // [2][kPartialStride][max_partial_blocks] block partials
     int64_t max_partial_blocks = 0;
     ups::RegState *state = nullptr;          // [2] registration state slots
     // ray tables
@@ -69,6 +69,11 @@ struct ups_context {
 namespace ups {
 
 constexpr int kPartialStride = 32;  // doubles per block partial
+
+// Block partials are stored by value: value v of block b at
+// partials[v * pstride + b], pstride = the block capacity rounded up to a
+// multiple of 16 (even, so that two consecutive blocks load as 16 bytes).
+inline int64_t partial_stride(int64_t blocks) { return (blocks + 15) / 16 * 16; }
 
 // Makes `dev` the current device for the scope and restores the caller's.
 struct DeviceGuard {

@@ -135,7 +135,7 @@ extern "C" ups_status ups_autotune(ups_context *ctx, const char *cache_json_path
         int *d_start = nullptr;
         RegState *state = nullptr;
         double *part = nullptr;
-        const int pstride = (int)((npix + kBlock - 1) / kBlock);
+        const int pstride = (int)partial_stride((npix + kBlock - 1) / kBlock);
         hipError_t e = hipMalloc(&surf, npix * copies * sizeof(float4));
         if (e == hipSuccess) e = hipMalloc(&d_inst, copies * sizeof(Inst));
         if (e == hipSuccess) e = hipMalloc(&d_start, (copies + 1) * sizeof(int));
