@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
-TRAFFIC_KIB = {"single": (2519.17, 64.17), "batch": (498116.73, 983.0)}
-TRAFFIC_SRC_HASH = "3d7f906046cd5cfc"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.56, 1.0
+TRAFFIC_KIB = {"single": (2385.84, 232.17), "batch": (498403.18, 3873.94)}
+TRAFFIC_SRC_HASH = "b7f2c37ab036b649"
 TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip", "ups_icp.hpp",
                "ups_device.hpp", "ups_internal.hpp")
 
