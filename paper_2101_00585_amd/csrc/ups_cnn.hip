@@ -4,7 +4,9 @@
 // Every convolution pass is an implicit GEMM on one tile engine: a 256-thread
 // block computes a 64 x 64 tile of C = A B, staging 64 x 16 slices of A and B
 // through LDS as bfloat16 and issuing v_mfma_f32_16x16x16_bf16 (each wavefront
-// owns a 32 x 32 quarter: 2 x 2 MFMA tiles).  Operand loaders gather A and B
+// owns a 32 x 32 quarter: 2 x 2 MFMA tiles).  The K loop takes slices of KB
+// (32, or 16 when K is at most 32) and loads the next slice into registers
+// while the matrix cores work on the current one.  Operand loaders gather A and B
 // straight from the NHWC activations, so no im2col buffer exists:
 //   forward          C[pixel_out][cout] = X_col[pixel_out][(tap,ci)] W[(tap,ci)][cout]
 //   backward (data)  C[pixel_in][ci]    = G_col[pixel_in][(tap,co)]  W[(tap,ci)][co]^T
@@ -28,42 +30,65 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-constexpr int kBM = 64, kBN = 64, kBK = 16, kLP = kBK + 4;  // LDS row pitch (elements): conflict-free b64 reads
+constexpr int kBM = 64, kBN = 64;
+constexpr int kSplitAlign = 16;                              // weight-gradient pixel chunks: multiples of this
 
 // One 64 x 64 tile: A rows m0.., B columns n0.., K range [k_begin, k_end).
 // LA::load(row, k, out[4]) / LB::load(col, k, out[4]) return bf16 values of
 // A(row, k..k+3) / B(k..k+3, col), zero outside the operand; ST::store(row,
 // col, v) writes one result.
-template <class LA, class LB, class ST>
+template <int KB = 32, class LA, class LB, class ST>
 __device__ __forceinline__ void mfma_tile(const LA &la, const LB &lb, const ST &st, int m0, int n0, int M, int N,
                                           int k_begin, int k_end) {
+    constexpr int kLP = KB + 4;  // LDS row pitch (elements), padded to spread the rows over the banks
+    constexpr int kQ = KB / 16;  // k quads per thread and operand in one slice
     __shared__ __align__(16) uint16_t As[kBM * kLP];
     __shared__ __align__(16) uint16_t Bs[kBN * kLP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int lr = tid >> 2, lq = tid & 3;  // loader: row / column lr of the tile, k quad lq
+    const int lr = tid >> 2, lq = tid & 3;  // loader: row / column lr of the tile, k quads lq + 4 q
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = k_begin; k0 < k_end; k0 += kBK) {
-        uint16_t a[4], b[4];
-        const int k = k0 + 4 * lq;
-        la.load(m0 + lr, k, k_end, a);
-        lb.load(n0 + lr, k, k_end, b);
-        *(uint2 *)&As[lr * kLP + 4 * lq] = make_uint2(a[0] | ((uint32_t)a[1] << 16), a[2] | ((uint32_t)a[3] << 16));
-        *(uint2 *)&Bs[lr * kLP + 4 * lq] = make_uint2(b[0] | ((uint32_t)b[1] << 16), b[2] | ((uint32_t)b[3] << 16));
+    uint16_t a[kQ][4], b[kQ][4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < kQ; q++) {
+            const int k = k0 + 4 * (lq + 4 * q);
+            la.load(m0 + lr, k, k_end, a[q]);
+            lb.load(n0 + lr, k, k_end, b[q]);
+        }
+    };
+    if (k_begin < k_end) fetch(k_begin);
+    for (int k0 = k_begin; k0 < k_end; k0 += KB) {
+#pragma unroll
+        for (int q = 0; q < kQ; q++) {
+            const int o = lr * kLP + 4 * (lq + 4 * q);
+            *(uint2 *)&As[o] = make_uint2(a[q][0] | ((uint32_t)a[q][1] << 16), a[q][2] | ((uint32_t)a[q][3] << 16));
+            *(uint2 *)&Bs[o] = make_uint2(b[q][0] | ((uint32_t)b[q][1] << 16), b[q][2] | ((uint32_t)b[q][3] << 16));
+        }
         __syncthreads();
-        bf16x4 fa[2], fb[2];
+        // the next slice's loads are in flight while this slice is multiplied
+        if (k0 + KB < k_end) fetch(k0 + KB);
+        // 16-wide chunks of the slice in ascending k: the same accumulation
+        // order as a loop over 16-wide slices
 #pragma unroll
-        for (int i = 0; i < 2; i++) fa[i] = *(const bf16x4 *)&As[(32 * wm + 16 * i + (lane & 15)) * kLP + 4 * (lane >> 4)];
+        for (int kc = 0; kc < kQ; kc++) {
+            bf16x4 fa[2], fb[2];
 #pragma unroll
-        for (int j = 0; j < 2; j++) fb[j] = *(const bf16x4 *)&Bs[(32 * wn + 16 * j + (lane & 15)) * kLP + 4 * (lane >> 4)];
+            for (int i = 0; i < 2; i++)
+                fa[i] = *(const bf16x4 *)&As[(32 * wm + 16 * i + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
 #pragma unroll
-        for (int i = 0; i < 2; i++)
+            for (int j = 0; j < 2; j++)
+                fb[j] = *(const bf16x4 *)&Bs[(32 * wn + 16 * j + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // D[4 (lane/16) + e][lane % 16] of each 16 x 16 tile
@@ -86,8 +111,14 @@ __device__ __forceinline__ void mfma_tile(const LA &la, const LB &lb, const ST &
 struct LoadIm2col {
     ConvShape c;
     const uint16_t *x;
+    float inv_cin;  // 1 / cin
+    // k / cin without an integer division: (k + 1/2) / cin lies at least
+    // 1 / (2 cin) away from an integer, and the FP32 product (below 9, as
+    // k < 9 cin) is within 9 * 2^-22 of it, so the truncation is exact for
+    // any cin below 2^17
+    __device__ __forceinline__ int tap_of(int k) const { return (int)(((float)k + 0.5f) * inv_cin); }
     __device__ __forceinline__ uint16_t at(int b, int oy, int ox, int k) const {
-        const int tap = k / c.cin, ci = k - tap * c.cin;
+        const int tap = tap_of(k), ci = k - tap * c.cin;
         const int ky = tap / 3, kx = tap - 3 * ky;
         const int iy = c.stride * oy + ky - 1;
         if (iy < 0 || iy >= c.h) return 0;
@@ -104,7 +135,7 @@ struct LoadIm2col {
         const int b = m / (c.ho * c.wo), r = m - b * c.ho * c.wo, oy = r / c.wo, ox = r - oy * c.wo;
         if ((c.cin & 3) == 0 && k + 3 < k_end) {
             // four channels of one tap: one 8-byte load
-            const int tap = k / c.cin, ci = k - tap * c.cin;
+            const int tap = tap_of(k), ci = k - tap * c.cin;
             const int ky = tap / 3, kx = tap - 3 * ky;
             const int iy = c.stride * oy + ky - 1;
             if (iy < 0 || iy >= c.h) {
@@ -115,6 +146,23 @@ struct LoadIm2col {
             ix = ix < 0 ? ix + c.w : (ix >= c.w ? ix - c.w : ix);
             const uint2 v = *(const uint2 *)&x[((size_t)(b * c.h + iy) * c.w + ix) * c.cin + ci];
             o[0] = v.x & 0xFFFF, o[1] = v.x >> 16, o[2] = v.y & 0xFFFF, o[3] = v.y >> 16;
+            return;
+        }
+        if ((c.cin & 1) == 0 && k + 3 < k_end) {
+            // even cin (k is a multiple of 4): two channel pairs, each of one tap
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                const int kk = k + 2 * p, tap = tap_of(kk), ci = kk - tap * c.cin;
+                const int ky = tap / 3, kx = tap - 3 * ky;
+                const int iy = c.stride * oy + ky - 1;
+                uint32_t v = 0;
+                if (iy >= 0 && iy < c.h) {
+                    int ix = c.stride * ox + kx - 1;
+                    ix = ix < 0 ? ix + c.w : (ix >= c.w ? ix - c.w : ix);
+                    v = *(const uint32_t *)&x[((size_t)(b * c.h + iy) * c.w + ix) * c.cin + ci];
+                }
+                o[2 * p] = v & 0xFFFF, o[2 * p + 1] = v >> 16;
+            }
             return;
         }
 #pragma unroll
@@ -132,6 +180,12 @@ struct LoadRowsBf16 {
             return;
         }
         const uint16_t *p = w + (size_t)n * K;
+        if ((K & 3) == 0 && k + 3 < k_end) {
+            // rows start on 8-byte boundaries: one 8-byte load
+            const uint2 v = *(const uint2 *)&p[k];
+            o[0] = v.x & 0xFFFF, o[1] = v.x >> 16, o[2] = v.y & 0xFFFF, o[3] = v.y >> 16;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 4; e++) o[e] = (k + e < k_end) ? p[k + e] : 0;
     }
@@ -146,11 +200,12 @@ struct StoreReluBf16 {
     }
 };
 
+template <int KB>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvShape c, const uint16_t *__restrict__ x,
                                                   const uint16_t *__restrict__ w_nk, const float *__restrict__ bias,
                                                   uint16_t *__restrict__ y) {
     const int M = c.n * c.ho * c.wo, N = c.cout, K = 9 * c.cin;
-    mfma_tile(LoadIm2col{c, x}, LoadRowsBf16{w_nk, N, K}, StoreReluBf16{bias, y, N}, blockIdx.x * kBM,
+    mfma_tile<KB>(LoadIm2col{c, x, 1.f / (float)c.cin}, LoadRowsBf16{w_nk, N, K}, StoreReluBf16{bias, y, N}, blockIdx.x * kBM,
               blockIdx.y * kBN, M, N, 0, K);
 }
 
@@ -290,8 +345,9 @@ ConvShape conv_shape(int n, int h, int w, int cin, int cout, int stride) {
 }
 
 ups_status conv_check(const ConvShape &c) {
-    UPS_REQUIRE(c.n >= 0 && c.h >= 1 && c.w >= 2 && c.cin >= 1 && c.cout >= 4 && (c.cout & 3) == 0,
-                "conv shape: need n >= 0, h >= 1, w >= 2, cin >= 1, cout a positive multiple of 4");
+    UPS_REQUIRE(c.n >= 0 && c.h >= 1 && c.w >= 2 && c.cin >= 1 && c.cin <= 65536 && c.cout >= 4 &&
+                    (c.cout & 3) == 0,
+                "conv shape: need n >= 0, h >= 1, w >= 2, 1 <= cin <= 65536, cout a positive multiple of 4");
     UPS_REQUIRE(c.stride == 1 || c.stride == 2, "conv stride must be 1 or 2");
     UPS_REQUIRE(c.w % c.stride == 0, "conv width must be a multiple of the stride");
     UPS_REQUIRE((int64_t)c.n * c.h * c.w * (c.cin > c.cout ? c.cin : c.cout) < ((int64_t)1 << 31),
@@ -303,7 +359,11 @@ ups_status launch_conv_fwd(const ConvShape &c, const uint16_t *x, const uint16_t
                            hipStream_t s) {
     const int M = c.n * c.ho * c.wo;
     if (M == 0) return UPS_OK;
-    hipLaunchKernelGGL(k_conv_fwd, dim3(cdiv(M, kBM), cdiv(c.cout, kBN)), dim3(256), 0, s, c, x, w_nk, b, y);
+    // a small K (the first layer's 9 x 2 = 18) wastes less in 16-wide slices
+    if (9 * c.cin <= 32)
+        hipLaunchKernelGGL(k_conv_fwd<16>, dim3(cdiv(M, kBM), cdiv(c.cout, kBN)), dim3(256), 0, s, c, x, w_nk, b, y);
+    else
+        hipLaunchKernelGGL(k_conv_fwd<32>, dim3(cdiv(M, kBM), cdiv(c.cout, kBN)), dim3(256), 0, s, c, x, w_nk, b, y);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
@@ -318,12 +378,12 @@ ups_status launch_conv_bwd_data(const ConvShape &c, const uint16_t *y, const flo
 }
 
 // Splits of the output pixels for the weight gradient: about 1024 blocks,
-// chunks a multiple of 16 and at least 64 pixels.
+// chunks a multiple of kSplitAlign and at least 64 pixels.
 static void wgt_split(const ConvShape &c, int &splits, int &chunk) {
     const int M = 9 * c.cin + 1, P = c.n * c.ho * c.wo;
     const int tiles = cdiv(M, kBM) * cdiv(c.cout, kBN);
     splits = std::max(1, std::min(256, cdiv(1024, tiles)));
-    chunk = std::max(64, cdiv(cdiv(std::max(P, 1), splits), kBK) * kBK);
+    chunk = std::max(64, cdiv(cdiv(std::max(P, 1), splits), kSplitAlign) * kSplitAlign);
     splits = cdiv(std::max(P, 1), chunk);
 }
 

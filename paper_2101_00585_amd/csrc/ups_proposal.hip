@@ -72,10 +72,15 @@ struct PropItem {
 
 // x[b][y][x][c] = bf16(1/r) of pixel (y rows/32, x cols/256) of image c, 0
 // where the range is not valid.
+// A block covers 256 pixels of one pair, so the pair's descriptor is
+// block-uniform (scalar loads).
 __global__ __launch_bounds__(256) void k_prop_input(const PropItem *__restrict__ items, int n, uint16_t *__restrict__ x) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n * kRows * kCols) return;
-    const int b = i / (kRows * kCols), q = i - b * (kRows * kCols), y = q / kCols, xx = q - y * kCols;
+    static_assert((kRows * kCols) % 256 == 0, "a block covers pixels of one pair");
+    constexpr int kBlocksPerPair = kRows * kCols / 256;
+    const int b = blockIdx.x / kBlocksPerPair;
+    if (b >= n) return;
+    const int q = (blockIdx.x - b * kBlocksPerPair) * 256 + threadIdx.x, y = q / kCols, xx = q - y * kCols;
+    const int i = b * (kRows * kCols) + q;
 #pragma unroll
     for (int c = 0; c < kIn; c++) {
         const RangeImg &im = items[b].img[c];
