@@ -431,7 +431,7 @@ ups_status ups_conv3x3_forward(int32_t n, int32_t h, int32_t w, int32_t cin, int
     if ((st = conv_check(c)) != UPS_OK) return st;
     if (n == 0) return UPS_OK;
     if ((st = check_ptr(x_d, 8, "x")) != UPS_OK) return st;
-    if ((st = check_ptr(w_nk_d, 2, "w")) != UPS_OK) return st;
+    if ((st = check_ptr(w_nk_d, 8, "w")) != UPS_OK) return st;
     if ((st = check_ptr(b_d, 4, "b")) != UPS_OK) return st;
     if ((st = check_ptr(y_d, 2, "y")) != UPS_OK) return st;
     return launch_conv_fwd(c, x_d, w_nk_d, b_d, y_d, (hipStream_t)stream);
@@ -467,7 +467,7 @@ ups_status ups_conv3x3_backward_weight(int32_t n, int32_t h, int32_t w, int32_t 
     if ((st = check_ptr(db_d, 4, "db")) != UPS_OK) return st;
     if ((st = check_ptr(work_d, 4, "work")) != UPS_OK) return st;
     if (n > 0) {
-        if ((st = check_ptr(x_d, 2, "x")) != UPS_OK) return st;
+        if ((st = check_ptr(x_d, 8, "x")) != UPS_OK) return st;
         if ((st = check_ptr(y_d, 2, "y")) != UPS_OK) return st;
         if ((st = check_ptr(dy_d, 4, "dy")) != UPS_OK) return st;
     }

@@ -73,3 +73,21 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert rc == -1
     rc = L.ups_classify_loop_closures(None, 4, None, 0.5, None, None, None)
     assert rc == -1
+
+
+def test_conv_arguments_rejected_on_host(lib):
+    """Convolution shapes and pointer alignment are checked before any device
+    work: cin above 65536, and a weight pointer that is not 8-byte aligned
+    (the forward pass loads four weights at a time)."""
+    import paper_2101_00585_amd as ups
+    L = ups.load()
+    L.ups_last_error.restype = ctypes.c_char_p
+    P = ctypes.c_void_p
+    args = (P(0x1000), P(0x2000), P(0x3000), P(0x4000), None)
+    fwd = L.ups_conv3x3_forward
+    fwd.argtypes = [ctypes.c_int32] * 6 + [P] * 5
+    assert fwd(1, 4, 8, 65537, 4, 1, *args) == -1
+    assert b"cin" in L.ups_last_error()
+    assert fwd(1, 4, 8, 4, 4, 1, P(0x1000), P(0x2002), P(0x3000), P(0x4000), None) == -1
+    assert b"w is not 8-byte aligned" in L.ups_last_error()
+    assert fwd(0, 4, 8, 4, 4, 1, *args) == 0  # empty batch: nothing to do
