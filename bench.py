@@ -276,7 +276,8 @@ def run_single(args, torch, ups, synth, W, stream):
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_bytes("single"),
                 "kernel": f"k_icp_one<2,{args.precision},iter> (level-0 Gauss-Newton launch, 128x1024)",
                 "launch_us": round(icp_us, 3), "algorithmic_bytes_per_launch": alg_bytes,
-                "note": "one 128x1024 registration: 4 MB per launch, cache-resident and latency bound"}
+                "note": "one 128x1024 registration: 4 MB per launch, cache-resident and latency bound; "
+                        "the HBM-bound form of the same kernel is the batched launch (batched.roofline)"}
     ctx.close()
     return dict(c1=c1, value=value, ms_per_step=ms_per_step, px_it=px_it, rot=rot, tr=tr, res=res,
                 roofline=roofline, valid_px_it=valid_px_it)
