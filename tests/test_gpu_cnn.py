@@ -31,9 +31,11 @@ def _np(t):
     return t.detach().to(torch.float64).cpu().numpy()
 
 
-# network layers plus shapes with ragged tiles, odd channel counts and stride 1
+# network layers plus shapes with ragged tiles, odd channel counts and stride 1;
+# between them every operand-gather path of the forward pass (four channels
+# per load, channel pairs, single channels) with 16- and 32-wide K slices
 SHAPES = [(2, h, w, cin, cout, s) for (h, w, cin, cout, s) in C.shapes()[0]] + [
-    (3, 6, 12, 3, 8, 1), (1, 5, 14, 6, 12, 2), (5, 4, 64, 16, 68, 2)]
+    (3, 6, 12, 3, 8, 1), (1, 5, 14, 6, 12, 2), (5, 4, 64, 16, 68, 2), (2, 4, 8, 5, 8, 1), (1, 3, 10, 1, 4, 2)]
 
 
 def _layer_case(shape, seed):
