@@ -495,11 +495,12 @@ ups_status ups_proposal_train_step(ups_proposal *p, int32_t n, const uint16_t *x
                                    float *loss_d, void *stream);
 
 /* The network's convolution as separate passes, for any shape (cout a
- * multiple of 4, 1 <= cin <= 65536, stride 1 or 2, width a multiple of the
- * stride; otherwise UPS_ERR_INVALID_ARG).  NHWC
- * tensors; x, y bfloat16 bits; dy, dx, dw, db FP32.  Device pointers: x and
- * the weights 8-byte aligned, the others aligned to their element size
- * (UPS_ERR_INVALID_ARG otherwise).
+ * multiple of 4 in [4, 65536], 1 <= cin <= 65536, stride 1 or 2, width a
+ * multiple of the stride; otherwise UPS_ERR_INVALID_ARG).  NHWC tensors;
+ * x, y bfloat16 bits; dy, dx, dw, db FP32.  Device pointers: x and the
+ * weights 8-byte aligned, and in the backward-data pass y 8-byte and dy
+ * 16-byte aligned (the kernels load four elements at a time); the others
+ * aligned to their element size (UPS_ERR_INVALID_ARG otherwise).
  *   forward:          y = relu(conv(x, W) + b), W given as w_nk[cout][9 cin]
  *                     (the transpose of the [9 cin][cout] layout), bfloat16;
  *   backward (data):  dx = dL/dx from y and dy = dL/dy, W as w_kn[9 cin][cout];

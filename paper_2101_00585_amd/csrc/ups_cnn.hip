@@ -222,21 +222,29 @@ struct LoadGradCol {
     ConvShape c;
     const float *dy;
     const uint16_t *y;
+    float inv_cout;  // 1 / cout: k / cout as in LoadIm2col::tap_of
     __device__ __forceinline__ void load(int m, int k, int k_end, uint16_t *o) const {
         o[0] = o[1] = o[2] = o[3] = 0;
         if (m >= c.n * c.h * c.w || k >= k_end) return;
         const int b = m / (c.h * c.w), r = m - b * c.h * c.w, iy = r / c.w, ix = r - iy * c.w;
         // cout is a multiple of 4: the four columns share a tap
-        const int tap = k / c.cout, co = k - tap * c.cout;
+        const int tap = (int)(((float)k + 0.5f) * inv_cout), co = k - tap * c.cout;
         const int ky = tap / 3, kx = tap - 3 * ky;
+        const int sh = c.stride >> 1;  // stride 1 or 2
         const int ty = iy + 1 - ky;
-        if (ty < 0 || ty % c.stride != 0 || ty / c.stride >= c.ho) return;
+        if (ty < 0 || (ty & sh) != 0 || (ty >> sh) >= c.ho) return;
         int tx = ix + 1 - kx;
         tx = tx < 0 ? tx + c.w : (tx >= c.w ? tx - c.w : tx);
-        if (tx % c.stride != 0 || tx / c.stride >= c.wo) return;
-        const size_t base = ((size_t)(b * c.ho + ty / c.stride) * c.wo + tx / c.stride) * c.cout + co;
+        if ((tx & sh) != 0 || (tx >> sh) >= c.wo) return;
+        const size_t base = ((size_t)(b * c.ho + (ty >> sh)) * c.wo + (tx >> sh)) * c.cout + co;
+        // four consecutive channels: one 8-byte load of y, one 16-byte load of dy
+        const uint2 yv = *(const uint2 *)&y[base];
+        const float4 g = *(const float4 *)&dy[base];
+        const uint16_t yy[4] = {(uint16_t)(yv.x & 0xFFFF), (uint16_t)(yv.x >> 16), (uint16_t)(yv.y & 0xFFFF),
+                                (uint16_t)(yv.y >> 16)};
+        const float gg[4] = {g.x, g.y, g.z, g.w};
 #pragma unroll
-        for (int e = 0; e < 4; e++) o[e] = grad_bf(dy, y, base + e);
+        for (int e = 0; e < 4; e++) o[e] = (yy[e] != 0 && !(yy[e] & 0x8000)) ? f2bf(gg[e]) : (uint16_t)0;
     }
 };
 
@@ -244,10 +252,11 @@ struct LoadGradCol {
 struct LoadWkn {
     ConvShape c;
     const uint16_t *w_kn;
+    float inv_cout;
     __device__ __forceinline__ void load(int n, int k, int k_end, uint16_t *o) const {
         o[0] = o[1] = o[2] = o[3] = 0;
         if (n >= c.cin || k >= k_end) return;
-        const int tap = k / c.cout, co = k - tap * c.cout;
+        const int tap = (int)(((float)k + 0.5f) * inv_cout), co = k - tap * c.cout;
         const uint2 v = *(const uint2 *)&w_kn[((size_t)tap * c.cin + n) * c.cout + co];
         o[0] = v.x & 0xFFFF, o[1] = v.x >> 16, o[2] = v.y & 0xFFFF, o[3] = v.y >> 16;
     }
@@ -263,8 +272,9 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(ConvShape c, const uint16
                                                        const float *__restrict__ dy,
                                                        const uint16_t *__restrict__ w_kn, float *__restrict__ dx) {
     const int M = c.n * c.h * c.w, N = c.cin, K = 9 * c.cout;
-    mfma_tile(LoadGradCol{c, dy, y}, LoadWkn{c, w_kn}, StoreF32{dx, N}, blockIdx.x * kBM, blockIdx.y * kBN, M, N, 0,
-              K);
+    const float inv_cout = 1.f / (float)c.cout;
+    mfma_tile(LoadGradCol{c, dy, y, inv_cout}, LoadWkn{c, w_kn, inv_cout}, StoreF32{dx, N}, blockIdx.x * kBM,
+              blockIdx.y * kBN, M, N, 0, K);
 }
 
 // ---------------------------------------------------- backward (weights)
@@ -276,23 +286,34 @@ struct LoadIm2colT {
     const uint16_t *x;
     __device__ __forceinline__ void load(int r, int k, int k_end, uint16_t *o) const {
         const int K9 = 9 * c.cin;
+        o[0] = o[1] = o[2] = o[3] = 0;
+        if (r > K9 || k >= k_end) return;
+        if (r == K9) {
+#pragma unroll
+            for (int e = 0; e < 4; e++) o[e] = (k + e < k_end) ? (uint16_t)0x3F80 : (uint16_t)0;  // 1.0
+            return;
+        }
+        const int tap = r / c.cin, ci = r - tap * c.cin;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        // the first pixel's (b, oy, ox) by division, the next three by stepping
+        int b = k / (c.ho * c.wo), q = k - b * c.ho * c.wo, oy = q / c.wo, ox = q - oy * c.wo;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int p = k + e;
-            o[e] = 0;
-            if (r > K9 || p >= k_end) continue;
-            if (r == K9) {
-                o[e] = 0x3F80;  // 1.0
-                continue;
+            if (k + e < k_end) {
+                const int iy = c.stride * oy + ky - 1;
+                if (iy >= 0 && iy < c.h) {
+                    int ix = c.stride * ox + kx - 1;
+                    ix = ix < 0 ? ix + c.w : (ix >= c.w ? ix - c.w : ix);
+                    o[e] = x[((size_t)(b * c.h + iy) * c.w + ix) * c.cin + ci];
+                }
             }
-            const int b = p / (c.ho * c.wo), q = p - b * c.ho * c.wo, oy = q / c.wo, ox = q - oy * c.wo;
-            const int tap = r / c.cin, ci = r - tap * c.cin;
-            const int ky = tap / 3, kx = tap - 3 * ky;
-            const int iy = c.stride * oy + ky - 1;
-            if (iy < 0 || iy >= c.h) continue;
-            int ix = c.stride * ox + kx - 1;
-            ix = ix < 0 ? ix + c.w : (ix >= c.w ? ix - c.w : ix);
-            o[e] = x[((size_t)(b * c.h + iy) * c.w + ix) * c.cin + ci];
+            if (++ox == c.wo) {
+                ox = 0;
+                if (++oy == c.ho) {
+                    oy = 0;
+                    b++;
+                }
+            }
         }
     }
 };
@@ -346,8 +367,8 @@ ConvShape conv_shape(int n, int h, int w, int cin, int cout, int stride) {
 
 ups_status conv_check(const ConvShape &c) {
     UPS_REQUIRE(c.n >= 0 && c.h >= 1 && c.w >= 2 && c.cin >= 1 && c.cin <= 65536 && c.cout >= 4 &&
-                    (c.cout & 3) == 0,
-                "conv shape: need n >= 0, h >= 1, w >= 2, 1 <= cin <= 65536, cout a positive multiple of 4");
+                    c.cout <= 65536 && (c.cout & 3) == 0,
+                "conv shape: need n >= 0, h >= 1, w >= 2, 1 <= cin <= 65536, cout a multiple of 4 in [4, 65536]");
     UPS_REQUIRE(c.stride == 1 || c.stride == 2, "conv stride must be 1 or 2");
     UPS_REQUIRE(c.w % c.stride == 0, "conv width must be a multiple of the stride");
     UPS_REQUIRE((int64_t)c.n * c.h * c.w * (c.cin > c.cout ? c.cin : c.cout) < ((int64_t)1 << 31),

@@ -444,8 +444,8 @@ ups_status ups_conv3x3_backward_data(int32_t n, int32_t h, int32_t w, int32_t ci
     ups_status st;
     if ((st = conv_check(c)) != UPS_OK) return st;
     if (n == 0) return UPS_OK;
-    if ((st = check_ptr(y_d, 2, "y")) != UPS_OK) return st;
-    if ((st = check_ptr(dy_d, 4, "dy")) != UPS_OK) return st;
+    if ((st = check_ptr(y_d, 8, "y")) != UPS_OK) return st;
+    if ((st = check_ptr(dy_d, 16, "dy")) != UPS_OK) return st;
     if ((st = check_ptr(w_kn_d, 8, "w")) != UPS_OK) return st;
     if ((st = check_ptr(dx_d, 4, "dx")) != UPS_OK) return st;
     return launch_conv_bwd_data(c, y_d, dy_d, w_kn_d, dx_d, (hipStream_t)stream);
