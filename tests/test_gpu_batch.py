@@ -224,3 +224,53 @@ def test_autotune_roundtrip(gpu_lib, bctx, tmp_path):
     c2 = gpu_lib.Context(0, max_pixels=1 << 16, max_batch=4, max_batch_pixels=1 << 20)
     gpu_lib.autotune(c2, path)
     c2.close()
+
+
+@pytest.mark.gpu
+def test_benchmark_batch_sampled_against_oracle(gpu_lib, bctx):
+    """The benchmark's own batch (the 256 pairs of the batch workload, its
+    parameters and its autotuned pixels per thread: the launch configuration
+    it times), with one registration of every size and scene kind compared
+    with the oracle.  The sampled pairs get oracle surfels on both sides (the
+    oracle's inputs never come from the GPU); the others GPU surfels, which
+    only fill the launches.  The iteration at which a level stops (update
+    norm below 1e-6) is not unique across FP32 and FP64 near the threshold,
+    so the counts are only checked for validity; the pose, the status and the
+    inlier count are compared."""
+    import os
+    import torch
+    pairs = W.batch(256)
+    sample = {}
+    for k, p in enumerate(pairs):
+        sample.setdefault((p["geom"].rows, p["geom"].cols, p["kind"]), k)
+    assert len(sample) == 8  # 4 sizes x 2 scene kinds
+    tune = os.path.join(os.path.dirname(gpu_lib.__file__), "autotune_gfx950.json")
+    gpu_lib.autotune(bctx, tune)
+    dev = torch.device("cuda:0")
+    items, ref_in = [], {}
+    for k, p in enumerate(pairs):
+        g = p["geom"]
+        if k in sample.values():
+            kf = O.panorama_normals(g, p["kf"]).astype(np.float32)
+            scan = O.panorama_normals(g, p["scan"]).astype(np.float32)
+            ref_in[k] = (kf, scan)
+            items.append(dict(scan_geom=g, kf_geom=g, scan_surfel=_t(scan), kf_surfel=_t(kf)))
+        else:
+            items.append(dict(scan_geom=g, kf_geom=g,
+                              scan_surfel=gpu_lib.panorama_normals(bctx, g, torch.from_numpy(p["scan"]).to(dev)),
+                              kf_surfel=gpu_lib.panorama_normals(bctx, g, torch.from_numpy(p["kf"]).to(dev))))
+    b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    res = gpu_lib.read_results(b.register([np.eye(4)] * len(items)))
+    b.close()
+    for (rows, cols, kind), k in sorted(sample.items()):
+        g = pairs[k]["geom"]
+        kf, scan = ref_in[k]
+        ref = O.register(g, scan, g, kf, np.eye(4), O.IcpParams(**BATCH_PARAMS))
+        rot, tr = synth.pose_error(res[k]["T"], ref["T"])
+        print(f"pair {k} {rows}x{cols} {kind}: GPU vs oracle {rot:.2e} rad {tr:.2e} m, "
+              f"iters {res[k]['iters_run']} / {ref['iters_run']}, status {res[k]['status']} / {ref['status']}",
+              flush=True)
+        assert rot < 1e-5 and tr < 1e-5, (k, rot, tr)
+        assert res[k]["status"] == ref["status"]
+        assert 1 <= res[k]["iters_run"] <= 30 and sum(res[k]["level_iters"]) == res[k]["iters_run"]
+        assert abs(res[k]["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
