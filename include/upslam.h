@@ -51,7 +51,7 @@ typedef enum {
     UPS_OK = 0,
     UPS_ERR_INVALID_ARG = -1, /* bad pointer, size, geometry or parameter */
     UPS_ERR_HIP = -2,         /* a HIP runtime call failed */
-    UPS_ERR_UNSUPPORTED = -3, /* valid request this build does not support */
+    UPS_ERR_UNSUPPORTED = -3, /* valid request the library does not support */
     UPS_ERR_WORKSPACE = -4    /* request exceeds what the context was created for */
 } ups_status;
 
