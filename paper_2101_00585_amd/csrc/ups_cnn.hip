@@ -353,6 +353,24 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight_reduce(int M, int N, in
     else db[i - r * N] = s;
 }
 
+// The same sums for few outputs and many splits (the first layers): one
+// wavefront per output, lane l adding splits l, l + 64, ... in order, then a
+// xor butterfly over the lanes (every lane ends with the same total).
+__global__ __launch_bounds__(256) void k_conv_bwd_weight_reduce_wave(int M, int N, int splits,
+                                                                     const float *__restrict__ part,
+                                                                     float *__restrict__ dw, float *__restrict__ db) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= M * N) return;  // uniform per wavefront
+    float s = 0.f;
+    for (int z = lane; z < splits; z += 64) s += part[(size_t)z * M * N + i];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane != 0) return;
+    const int r = i / N;
+    if (r < M - 1) dw[i] = s;
+    else db[i - r * N] = s;
+}
+
 // ------------------------------------------------------------ host side
 
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -426,8 +444,12 @@ ups_status launch_conv_bwd_weight(const ConvShape &c, const uint16_t *x, const u
                            dy, chunk, work);
         UPS_CHECK_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_conv_bwd_weight_reduce, dim3(cdiv(M * c.cout, 256)), dim3(256), 0, s, M, c.cout,
-                       P > 0 ? splits : 0, work, dw, db);
+    if (M * c.cout <= 32768 && splits >= 64)
+        hipLaunchKernelGGL(k_conv_bwd_weight_reduce_wave, dim3(cdiv(M * c.cout, 4)), dim3(256), 0, s, M, c.cout,
+                           P > 0 ? splits : 0, work, dw, db);
+    else
+        hipLaunchKernelGGL(k_conv_bwd_weight_reduce, dim3(cdiv(M * c.cout, 256)), dim3(256), 0, s, M, c.cout,
+                           P > 0 ? splits : 0, work, dw, db);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
