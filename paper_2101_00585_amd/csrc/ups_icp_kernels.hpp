@@ -560,10 +560,20 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix
 // table of tile counts (tile_start[n] = total blocks).
+// Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and
+// each XCD has its own L2: the tiles are permuted so that the workgroups of
+// one XCD take a contiguous run of tiles, and neighbouring tiles of a
+// registration, whose keyframe gathers share cache lines, meet in one L2.
+// Any other dealing still covers every tile once.
+__device__ __forceinline__ int xcd_tile(int blk, int nblk) {
+    const int x = blk & 7, q = blk >> 3, per = nblk >> 3, rem = nblk & 7;
+    return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+}
+
 template <int K, int PREC, int MODE, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
                                                       const int *__restrict__ tile_start, int n, StepArgs a) {
-    const int b = blockIdx.x;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
     int lo = 0, hi = n;  // the last k with tile_start[k] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
