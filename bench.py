@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.94, 1.0
-TRAFFIC_KIB = {"single": (2385.84, 232.17), "batch": (496598.45, 1046.51)}
-TRAFFIC_SRC_HASH = "e99d531e2d6a95f1"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
+TRAFFIC_KIB = {"single": (2081.39, 58.17), "batch": (496609.39, 1075.96)}
+TRAFFIC_SRC_HASH = "c0348516e23afe6f"
 TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip", "ups_icp.hpp",
                "ups_device.hpp", "ups_internal.hpp")
 

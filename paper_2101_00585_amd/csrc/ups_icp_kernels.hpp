@@ -553,13 +553,6 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     }
 }
 
-template <int K, int PREC, int MODE, bool WORLD, bool IRLS>
-__global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
-    icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, blockIdx.x);
-}
-
-// Batch: block -> (registration, tile) by binary search in the level's prefix
-// table of tile counts (tile_start[n] = total blocks).
 // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and
 // each XCD has its own L2: the tiles are permuted so that the workgroups of
 // one XCD take a contiguous run of tiles, and neighbouring tiles of a
@@ -570,6 +563,13 @@ __device__ __forceinline__ int xcd_tile(int blk, int nblk) {
     return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
 }
 
+template <int K, int PREC, int MODE, bool WORLD, bool IRLS>
+__global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
+    icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Batch: block -> (registration, tile) by binary search in the level's prefix
+// table of tile counts (tile_start[n] = total blocks).
 template <int K, int PREC, int MODE, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
                                                       const int *__restrict__ tile_start, int n, StepArgs a) {
