@@ -13,6 +13,7 @@ import pytest
 import oracle as O
 import synth
 from synth import workloads as W
+from quality_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
 
 pytestmark = pytest.mark.gpu
 
@@ -274,3 +275,9 @@ def test_benchmark_batch_sampled_against_oracle(gpu_lib, bctx):
         assert res[k]["status"] == ref["status"]
         assert 1 <= res[k]["iters_run"] <= 30 and sum(res[k]["level_iters"]) == res[k]["iters_run"]
         assert abs(res[k]["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
+        # the quality block (inlier ratio, rms, truncated cost) at the two final poses
+        mism = quality_mismatches(gpu_lib, bctx, g, scan, kf, res[k]["T"], ref["T"])
+        rr = O.residuals(g, scan, g, kf, ref["T"])
+        dr = pose_displacement_bound(res[k]["T"], ref["T"], float(scan[..., 3].max()))
+        print(f"   truncated cost {res[k]['trunc_cost']:.6f} / {ref['trunc_cost']:.6f}, mismatches {mism}", flush=True)
+        assert_quality_close(res[k], ref, mism, 0.5, dr, float(np.abs(rr["r"][rr["inlier"]]).sum()))

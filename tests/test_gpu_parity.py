@@ -16,6 +16,7 @@ import oracle as O
 import synth
 from synth import lidar_geom, se3, rot_z, rot_x
 from synth import workloads as W
+from quality_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
 
 pytestmark = pytest.mark.gpu
 
@@ -217,13 +218,42 @@ def test_register_config0_matches_oracle(gpu_lib, ctx, c0, c0_surfels):
     g = c0["geom"]
     res, ref = _register_both(gpu_lib, ctx, g, kf, scan, np.eye(4), gpu_lib.IcpParams(), O.IcpParams())
     rot, tr = synth.pose_error(res["T"], ref["T"])
-    print(f"config0 GPU vs oracle: {rot:.3e} rad {tr:.3e} m; inliers {res['inliers']} vs {ref['inliers']}")
+    print(f"config0 GPU vs oracle: {rot:.3e} rad {tr:.3e} m; inliers {res['inliers']} vs {ref['inliers']}; "
+          f"truncated cost {res['trunc_cost']:.6f} vs {ref['trunc_cost']:.6f}")
     assert res["status"] == ref["status"] == 0
     assert res["iters_run"] == ref["iters_run"] == 20
     assert rot < ROT_TOL and tr < TR_TOL, (rot, tr)
     assert abs(res["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
-    assert res["valid"] == ref["valid"]
-    assert abs(res["rms"] - ref["rms"]) < 1e-3 * ref["rms"] + 1e-6
+    # the quality block at the two final poses
+    mism = quality_mismatches(gpu_lib, ctx, g, scan, kf, res["T"], ref["T"])
+    rr = O.residuals(g, scan, g, kf, ref["T"])
+    dr = pose_displacement_bound(res["T"], ref["T"], float(scan[..., 3].max()))
+    assert_quality_close(res, ref, mism, 0.5, dr, float(np.abs(rr["r"][rr["inlier"]]).sum()))
+
+
+@pytest.mark.parametrize("case", ["truth", "perturbed", "self", "far"])
+def test_quality_fixed_pose_matches_oracle(gpu_lib, ctx, c0, c0_surfels, case):
+    """The quality block alone (a registration with no iterations evaluates it
+    at its start pose) at the same pose on both sides: inlier ratio, rms and
+    truncated cost within what the counted correspondence mismatches allow."""
+    kf, scan = c0_surfels
+    g = c0["geom"]
+    T = {"truth": c0["T_gt"], "perturbed": c0["T_gt"] @ O.exp_se3([0.01, -0.004, 0.002, 0.08, -0.05, 0.02]),
+         "self": np.eye(4), "far": se3(np.eye(3), [0.0, 0.0, 40.0])}[case]
+    if case == "self":
+        kf = scan
+    p = dict(levels=3, iters=(0, 0, 0), d_max=(0.5, 1.0, 2.0))
+    res, ref = _register_both(gpu_lib, ctx, g, kf, scan, T, gpu_lib.IcpParams(**p), O.IcpParams(**p))
+    assert res["iters_run"] == ref["iters_run"] == 0
+    assert np.array_equal(res["T"], T)
+    mism = quality_mismatches(gpu_lib, ctx, g, scan, kf, T, T)
+    print(f"{case}: inliers {res['inliers']} / {ref['inliers']}, truncated cost {res['trunc_cost']:.6f} / "
+          f"{ref['trunc_cost']:.6f}, rms {res['rms']:.6e} / {ref['rms']:.6e}, mismatches {mism}")
+    assert_quality_close(res, ref, mism, 0.5)
+    if case == "self":
+        assert mism == 0 and res["rms"] == 0.0 and res["trunc_cost"] == ref["trunc_cost"]
+    if case == "far":
+        assert res["inliers"] == 0 and res["trunc_cost"] == ref["trunc_cost"] == 0.25 * ref["valid"]
 
 
 def test_register_f64_mode_matches_oracle(gpu_lib, ctx, c0, c0_surfels):
