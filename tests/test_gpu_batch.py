@@ -13,7 +13,7 @@ import pytest
 import oracle as O
 import synth
 from synth import workloads as W
-from quality_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
+from parity_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
 
 pytestmark = pytest.mark.gpu
 

@@ -22,7 +22,8 @@ import pytest
 
 import oracle as O
 import synth
-from quality_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
+from parity_checks import (assert_fusion_close, assert_quality_close, fusion_ambiguous, pose_displacement_bound,
+                           quality_mismatches)
 from synth import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -92,15 +93,13 @@ def test_config1_identical_inputs(gpu_lib, ctx, c1, orc):
     gpu_lib.fuse_scan(ctx, g, _t(scan), g, kf_d, cnt_d, res["T"])
     ko, co = O.fuse(g, scan, g, kf, cnt, ref["T"])
     kg, cg = _np(kf_d), _np(cnt_d).view(np.uint16)
-    mism_c = int((cg != co).sum())
-    print(f"fusion: {mism_c} count mismatches of {cg.size}", flush=True)
-    assert mism_c <= 2e-3 * cg.size, mism_c
-    same = (cg == co) & (co > 0)
+    amb = fusion_ambiguous(g, scan.astype(np.float64), g, kf.astype(np.float64), cnt, ref["T"])
+    n_diff, n_amb, n_bad = assert_fusion_close(kg, cg, ko, co, amb)
+    print(f"fusion: {n_diff} keyframe pixels differ, {n_amb} at a projection or gate boundary, "
+          f"{n_bad} unexplained; {int((co > cnt).sum())} counts raised", flush=True)
+    assert n_bad == 0 and n_diff <= 2e-3 * cg.size
     # pixels seen by all 10 keyframe scans stay at the saturated count
-    assert same.sum() > 0.5 * cg.size and (co > cnt).sum() > 0.1 * cg.size
-    dr_f = np.abs(kg[..., 3][same] - ko[..., 3][same]) / ko[..., 3][same]
-    dn_f = np.linalg.norm(kg[same][:, :3] - ko[same][:, :3], axis=-1)
-    assert dr_f.max() < 1e-5 and dn_f.max() < 1e-4, (dr_f.max(), dn_f.max())
+    assert (co > cnt).sum() > 0.1 * cg.size
 
 
 def test_config1_pipeline_stages(gpu_lib, ctx, c1, orc):

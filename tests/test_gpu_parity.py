@@ -16,7 +16,7 @@ import oracle as O
 import synth
 from synth import lidar_geom, se3, rot_z, rot_x
 from synth import workloads as W
-from quality_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
+from parity_checks import assert_quality_close, pose_displacement_bound, quality_mismatches
 
 pytestmark = pytest.mark.gpu
 
