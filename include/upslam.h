@@ -191,6 +191,22 @@ ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const flo
                              const ups_geom *kf_g, const float *kf_surfel_d, const ups_pose *init_d,
                              const ups_icp_params *p, ups_icp_result *result_d, void *stream);
 
+/* ups_register_scan for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * no context, no allocation.  Same arguments (minus the context), numerics,
+ * result and errors as ups_register_scan; it runs on the calling thread's
+ * current device, and `stream` (NULL = the default stream) must belong to it.
+ * Its scratch (both panoramas' ray tables and pyramids, the block partials
+ * and the registration state, 3.6 MB) is a static array in device memory
+ * that each GPU holds from the library's first use until the process ends;
+ * scan and keyframe are limited to 262144 pixels each (e.g. 128 x 2048):
+ * larger ones return UPS_ERR_WORKSPACE.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (different streams or
+ * threads) race and must be ordered by the caller.  Enqueues only kernels. */
+ups_status ups_register_scan_noalloc(const ups_geom *scan_g, const float *scan_surfel_d, const ups_geom *kf_g,
+                                     const float *kf_surfel_d, const ups_pose *init_d, const ups_icp_params *p,
+                                     ups_icp_result *result_d, void *stream);
+
 /* Fuse a registered sweep into a keyframe in place (Section III-C).  T_d: device
  * pose scan -> keyframe (e.g. &result_d->T).  kf_surfel_d / kf_count_d are
  * read and written; the sweep's surfel image is only read. */

@@ -103,6 +103,7 @@ def load():
         "ups_panorama_normals": [_P, _P, _P, _P, _P, _P],
         "ups_pyramid_level": [_P, _P, _P, ctypes.c_int32, _P, _P],
         "ups_register_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
+        "ups_register_scan_noalloc": [_P, _P, _P, _P, _P, _P, _P, _P],
         "ups_fuse_scan": [_P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_correspondences": [_P, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
         "ups_register_scan_world": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
@@ -363,6 +364,25 @@ def register_scan(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, init
                                             _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
                                             _dev_ptr(result, torch.uint8, "result"), _stream()))
     result._keep_init = init_t  # keep a host-made init alive until the stream consumes it
+    return result
+
+
+def register_scan_noalloc(scan_geom, scan_surfel, kf_geom, kf_surfel, init, params: IcpParams | None = None,
+                          result=None):
+    """``register_scan`` through the entry point that allocates nothing (its
+    scratch is a static device array; panoramas up to 262144 pixels), on the
+    current device.  ``init`` and ``result`` as for ``register_scan``."""
+    torch = _torch()
+    p = (params or IcpParams()).c()
+    if result is None:
+        result = new_result(scan_surfel.device)
+    init_t = init if isinstance(init, torch.Tensor) else pose_tensor(init, scan_surfel.device)
+    sg, kg = geom_c(scan_geom), geom_c(kf_geom)
+    _check(_LIB.ups_register_scan_noalloc(ctypes.byref(sg), _dev_ptr(scan_surfel, torch.float32, "scan surfel"),
+                                          ctypes.byref(kg), _dev_ptr(kf_surfel, torch.float32, "keyframe surfel"),
+                                          _dev_ptr(init_t, torch.float64, "init pose"), ctypes.byref(p),
+                                          _dev_ptr(result, torch.uint8, "result"), _stream()))
+    result._keep_init = init_t
     return result
 
 

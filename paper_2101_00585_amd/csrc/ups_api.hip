@@ -25,7 +25,7 @@ ups_status check_ptr(const void *p, size_t align, const char *what) {
 }
 
 
-static ups_status check_geom(const ups_geom *g, const char *what) {
+ups_status check_geom(const ups_geom *g, const char *what) {
     UPS_REQUIRE(g != nullptr, std::string(what) + " geometry is null");
     UPS_REQUIRE(g->rows >= 2 && g->rows <= 4096, std::string(what) + ": rows must be in [2, 4096]");
     UPS_REQUIRE(g->cols >= 64 && g->cols <= 16384 && g->cols % 64 == 0,
@@ -72,6 +72,11 @@ ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream
             e = &ctx->luts.back();
         }
     }
+    *out = geom_view(g, level, e->row, e->col);
+    return UPS_OK;
+}
+
+DGeom geom_view(const ups_geom *g, int level, const float2 *lut_row, const float2 *lut_col) {
     const int s = 1 << level;
     DGeom d;
     d.rows = g->rows >> level;
@@ -88,9 +93,34 @@ ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream
         const double top = g->el_top + half, bottom = g->el_top - (d.rows - 1) * dl - half;
         d.narrow = (top < M_PI / 4 - 1e-6 && bottom > -M_PI / 4 + 1e-6) ? 1 : 0;
     }
-    d.lut_row = e->row;
-    d.lut_col = e->col;
-    *out = d;
+    d.lut_row = lut_row;
+    d.lut_col = lut_col;
+    return d;
+}
+
+ups_status check_icp_params(const ups_icp_params *p) {
+    UPS_REQUIRE(p != nullptr, "icp params is null");
+    UPS_REQUIRE(p->levels >= 1 && p->levels <= 4, "levels must be in [1, 4]");
+    for (int l = 0; l < p->levels; l++) {
+        UPS_REQUIRE(p->iters[l] >= 0 && p->iters[l] <= 1000, "iters must be in [0, 1000]");
+        UPS_REQUIRE(p->d_max[l] > 0.f && std::isfinite(p->d_max[l]), "d_max must be > 0");
+    }
+    UPS_REQUIRE(p->cos_theta_max >= -1.f && p->cos_theta_max <= 1.f, "cos_theta_max must be in [-1, 1]");
+    UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
+    UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
+    UPS_REQUIRE(p->irls_delta == 0.f || (p->irls_delta >= 1e-6f && std::isfinite(p->irls_delta)),
+                "irls_delta must be 0 or a finite value >= 1e-6");
+    UPS_REQUIRE(p->irls_delta == 0.f || p->precision == UPS_PREC_KAHAN_F64,
+                "the IRLS objective (irls_delta > 0) needs precision UPS_PREC_KAHAN_F64");
+    return UPS_OK;
+}
+
+ups_status check_levels(const ups_geom *g, int levels, const char *what) {
+    const int s = 1 << (levels - 1);
+    UPS_REQUIRE(g->rows % s == 0 && g->rows / s >= 2,
+                std::string(what) + ": rows must be divisible by 2^(levels-1)");
+    UPS_REQUIRE(g->cols % (64 * s) == 0,
+                std::string(what) + ": cols must be divisible by 64 * 2^(levels-1)");
     return UPS_OK;
 }
 
@@ -189,32 +219,6 @@ ups_status ups_pyramid_level(ups_context *ctx, const ups_geom *g, const float *s
     DGeom d0;
     if ((st = device_geom(ctx, g, 0, (hipStream_t)stream, &d0)) != UPS_OK) return st;
     return launch_subsample(d0, (const float4 *)surfel_d, level, (float4 *)out_d, (hipStream_t)stream);
-}
-
-static ups_status check_icp_params(const ups_icp_params *p) {
-    UPS_REQUIRE(p != nullptr, "icp params is null");
-    UPS_REQUIRE(p->levels >= 1 && p->levels <= 4, "levels must be in [1, 4]");
-    for (int l = 0; l < p->levels; l++) {
-        UPS_REQUIRE(p->iters[l] >= 0 && p->iters[l] <= 1000, "iters must be in [0, 1000]");
-        UPS_REQUIRE(p->d_max[l] > 0.f && std::isfinite(p->d_max[l]), "d_max must be > 0");
-    }
-    UPS_REQUIRE(p->cos_theta_max >= -1.f && p->cos_theta_max <= 1.f, "cos_theta_max must be in [-1, 1]");
-    UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
-    UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
-    UPS_REQUIRE(p->irls_delta == 0.f || (p->irls_delta >= 1e-6f && std::isfinite(p->irls_delta)),
-                "irls_delta must be 0 or a finite value >= 1e-6");
-    UPS_REQUIRE(p->irls_delta == 0.f || p->precision == UPS_PREC_KAHAN_F64,
-                "the IRLS objective (irls_delta > 0) needs precision UPS_PREC_KAHAN_F64");
-    return UPS_OK;
-}
-
-static ups_status check_levels(const ups_geom *g, int levels, const char *what) {
-    const int s = 1 << (levels - 1);
-    UPS_REQUIRE(g->rows % s == 0 && g->rows / s >= 2,
-                std::string(what) + ": rows must be divisible by 2^(levels-1)");
-    UPS_REQUIRE(g->cols % (64 * s) == 0,
-                std::string(what) + ": cols must be divisible by 64 * 2^(levels-1)");
-    return UPS_OK;
 }
 
 // world_kf: null for the keyframe-frame path, else the keyframe's world pose.

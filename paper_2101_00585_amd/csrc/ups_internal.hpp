@@ -92,7 +92,14 @@ struct DeviceGuard {
 // Validate a geometry and return its device view at pyramid level `level`
 // (ray tables are uploaded on first use of the geometry).
 ups_status device_geom(ups_context *ctx, const ups_geom *g, int level, hipStream_t stream, DGeom *out);
+// The device view of a validated geometry at `level` over given level-0 ray
+// tables (lut_row[rows], lut_col[cols]: (cos, sin) of elevations / azimuths).
+DGeom geom_view(const ups_geom *g, int level, const float2 *lut_row, const float2 *lut_col);
 ups_status check_ptr(const void *p, size_t align, const char *what);
+ups_status check_geom(const ups_geom *g, const char *what);
+ups_status check_icp_params(const ups_icp_params *p);
+// rows and cols of g divisible by 2^(levels-1), cols by 64 * 2^(levels-1)
+ups_status check_levels(const ups_geom *g, int levels, const char *what);
 // Autotuned pixels per thread for batch launches over panoramas of about npix
 // pixels (0 when ups_autotune has not run).
 int autotuned_k(ups_context *ctx, int64_t npix);

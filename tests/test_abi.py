@@ -91,3 +91,29 @@ def test_conv_arguments_rejected_on_host(lib):
     assert fwd(1, 4, 8, 4, 4, 1, P(0x1000), P(0x2002), P(0x3000), P(0x4000), None) == -1
     assert b"w is not 8-byte aligned" in L.ups_last_error()
     assert fwd(0, 4, 8, 4, 4, 1, *args) == 0  # empty batch: nothing to do
+
+
+def test_noalloc_limits_rejected_on_host(lib):
+    """The entry point without a context rejects panoramas above its static
+    scratch (262144 pixels) and invalid parameters before any device work."""
+    import paper_2101_00585_amd as ups
+    L = ups.load()
+    L.ups_last_error.restype = ctypes.c_char_p
+    P = ctypes.c_void_p
+    small = ups.ups_geom(128, 2048, 0.39, 0.0062, 0.0, 50.0)
+    big = ups.ups_geom(256, 2048, 0.39, 0.0031, 0.0, 50.0)
+    p = ups.IcpParams(levels=3, iters=(10, 10, 10)).c()
+    bufs = (P(0x10000), P(0x20000), P(0x30000), P(0x40000))
+    rc = L.ups_register_scan_noalloc(ctypes.byref(big), bufs[0], ctypes.byref(small), bufs[1], bufs[2],
+                                     ctypes.byref(p), bufs[3], None)
+    assert rc == -4 and b"262144 pixels" in L.ups_last_error()
+    rc = L.ups_register_scan_noalloc(ctypes.byref(small), bufs[0], ctypes.byref(big), bufs[1], bufs[2],
+                                     ctypes.byref(p), bufs[3], None)
+    assert rc == -4
+    bad = ups.IcpParams(levels=5).c()
+    rc = L.ups_register_scan_noalloc(ctypes.byref(small), bufs[0], ctypes.byref(small), bufs[1], bufs[2],
+                                     ctypes.byref(bad), bufs[3], None)
+    assert rc == -1
+    rc = L.ups_register_scan_noalloc(ctypes.byref(small), P(0x10004), ctypes.byref(small), bufs[1], bufs[2],
+                                     ctypes.byref(p), bufs[3], None)
+    assert rc == -1 and b"aligned" in L.ups_last_error()
