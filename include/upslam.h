@@ -489,6 +489,22 @@ ups_status ups_proposal_load(ups_proposal *p, const char *path);
 /* Gradient of the last training step. */
 ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n);
 
+/* Resumable training state to / from a file: the 8 bytes "UPSCKP01", the
+ * parameter count and the Adam step count (little-endian int64), then the
+ * FP32 parameters, first moments and second moments.  A training step after
+ * load_checkpoint continues exactly as it would have after save_checkpoint
+ * (the caller keeps its own data order and random state).  load rejects any
+ * other content with UPS_ERR_INVALID_ARG and leaves the network unchanged.
+ * Synchronous. */
+ups_status ups_proposal_save_checkpoint(ups_proposal *p, const char *path);
+ups_status ups_proposal_load_checkpoint(ups_proposal *p, const char *path);
+
+/* Diagnostics: the stored output of convolution layer `layer` (1..5, NHWC,
+ * bfloat16 bits) for the first n pairs of the last forward pass or training
+ * step (act_h), and its gradient dL/dy (FP32) from the last training step
+ * (dact_h); either may be NULL.  Host buffers; synchronous. */
+ups_status ups_proposal_activations(ups_proposal *p, int32_t layer, int32_t n, uint16_t *act_h, float *dact_h);
+
 /* Record the n (keyframe, scan) image pairs ups_proposal_input reads
  * (synchronous upload of n descriptors; the images must stay alive). */
 ups_status ups_proposal_plan_input(ups_proposal *p, int32_t n, const ups_range_image *kf_h,

@@ -130,6 +130,9 @@ def load():
         "ups_proposal_set_params": [_P, _P, i64],
         "ups_proposal_get_params": [_P, _P, i64],
         "ups_proposal_get_grads": [_P, _P, i64],
+        "ups_proposal_save_checkpoint": [_P, ctypes.c_char_p],
+        "ups_proposal_load_checkpoint": [_P, ctypes.c_char_p],
+        "ups_proposal_activations": [_P, i32, i32, _P, _P],
         "ups_proposal_save": [_P, ctypes.c_char_p],
         "ups_proposal_load": [_P, ctypes.c_char_p],
         "ups_proposal_plan_input": [_P, i32, _P, _P],
@@ -792,6 +795,28 @@ class Proposal:
         a = np.empty(self.n_params, dtype=np.float32)
         _check(_LIB.ups_proposal_get_grads(self._h, a.ctypes.data_as(_P), int(a.size)))
         return a
+
+    def save_checkpoint(self, path: str):
+        """Parameters, Adam moments and step count to ``path``."""
+        _check(_LIB.ups_proposal_save_checkpoint(self._h, os.fsencode(path)))
+
+    def load_checkpoint(self, path: str):
+        """Resume from a file written by ``save_checkpoint``."""
+        _check(_LIB.ups_proposal_load_checkpoint(self._h, os.fsencode(path)))
+
+    # NHWC shapes of the five convolution outputs
+    ACT_SHAPES = ((16, 128, 32), (8, 64, 64), (4, 32, 96), (2, 16, 128), (2, 16, 128))
+
+    def activations(self, layer: int, n: int):
+        """(stored output of convolution layer ``layer`` (1..5) as float64
+        values of its bfloat16 bits, its FP32 gradient from the last training
+        step), each [n, h, w, c]."""
+        shape = (n,) + self.ACT_SHAPES[layer - 1]
+        a = np.empty(shape, dtype=np.uint16)
+        d = np.empty(shape, dtype=np.float32)
+        _check(_LIB.ups_proposal_activations(self._h, int(layer), int(n), a.ctypes.data_as(_P),
+                                             d.ctypes.data_as(_P)))
+        return (a.astype(np.uint32) << 16).view(np.float32).astype(np.float64), d.astype(np.float64)
 
     def plan_input(self, kf_sources, scan_sources, kf_geoms=None, scan_geoms=None):
         """Record (keyframe, scan) range sources (tensors, see range_image)."""

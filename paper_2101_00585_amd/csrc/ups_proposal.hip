@@ -311,6 +311,76 @@ ups_status ups_proposal_load(ups_proposal *p, const char *path) {
     return ups_proposal_set_params(p, h.data(), n);
 }
 
+// Checkpoint file: the 8 bytes "UPSCKP01", the parameter count and the Adam
+// step count as little-endian int64, then the FP32 parameters, first moments
+// and second moments in the layout's order.
+static const char kCkptMagic[8] = {'U', 'P', 'S', 'C', 'K', 'P', '0', '1'};
+
+ups_status ups_proposal_save_checkpoint(ups_proposal *p, const char *path) {
+    UPS_REQUIRE(p && path, "null argument");
+    const int64_t n = layout().total;
+    std::vector<float> h(3 * n);
+    DeviceGuard g(p->device);
+    UPS_CHECK_HIP(g.err);
+    UPS_CHECK_HIP(hipDeviceSynchronize());
+    UPS_CHECK_HIP(hipMemcpy(h.data(), p->params, n * sizeof(float), hipMemcpyDeviceToHost));
+    UPS_CHECK_HIP(hipMemcpy(h.data() + n, p->m, n * sizeof(float), hipMemcpyDeviceToHost));
+    UPS_CHECK_HIP(hipMemcpy(h.data() + 2 * n, p->v, n * sizeof(float), hipMemcpyDeviceToHost));
+    FILE *f = fopen(path, "wb");
+    UPS_REQUIRE(f != nullptr, std::string("cannot open ") + path + " for writing");
+    const int64_t step = p->step;
+    const bool ok = fwrite(kCkptMagic, 1, 8, f) == 8 && fwrite(&n, sizeof(n), 1, f) == 1 &&
+                    fwrite(&step, sizeof(step), 1, f) == 1 && fwrite(h.data(), sizeof(float), 3 * n, f) == (size_t)(3 * n);
+    const bool closed = fclose(f) == 0;
+    UPS_REQUIRE(ok && closed, std::string("write to ") + path + " failed");
+    return UPS_OK;
+}
+
+ups_status ups_proposal_load_checkpoint(ups_proposal *p, const char *path) {
+    UPS_REQUIRE(p && path, "null argument");
+    const int64_t n = layout().total;
+    FILE *f = fopen(path, "rb");
+    UPS_REQUIRE(f != nullptr, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t m = -1, step = -1;
+    std::vector<float> h(3 * n);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kCkptMagic, 8) == 0 && fread(&m, sizeof(m), 1, f) == 1 &&
+              m == n && fread(&step, sizeof(step), 1, f) == 1 && step >= 0 &&
+              fread(h.data(), sizeof(float), 3 * n, f) == (size_t)(3 * n);
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;
+    fclose(f);
+    UPS_REQUIRE(ok, std::string(path) + " is not a checkpoint of this network");
+    DeviceGuard g(p->device);
+    UPS_CHECK_HIP(g.err);
+    UPS_CHECK_HIP(hipDeviceSynchronize());
+    UPS_CHECK_HIP(hipMemcpy(p->params, h.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    UPS_CHECK_HIP(hipMemcpy(p->m, h.data() + n, n * sizeof(float), hipMemcpyHostToDevice));
+    UPS_CHECK_HIP(hipMemcpy(p->v, h.data() + 2 * n, n * sizeof(float), hipMemcpyHostToDevice));
+    p->step = step;
+    ups_status st = pack_all(p, nullptr);
+    if (st != UPS_OK) return st;
+    UPS_CHECK_HIP(hipDeviceSynchronize());
+    return UPS_OK;
+}
+
+ups_status ups_proposal_activations(ups_proposal *p, int32_t layer, int32_t n, uint16_t *act_h, float *dact_h) {
+    UPS_REQUIRE(p, "null argument");
+    UPS_REQUIRE(layer >= 1 && layer <= kLayers, "layer must be in [1, 5]");
+    ups_status st;
+    if ((st = check_n(p, n)) != UPS_OK) return st;
+    const Layout &L = layout();
+    const size_t count = (size_t)n * L.h[layer] * L.w[layer] * kCout[layer - 1];
+    DeviceGuard g(p->device);
+    UPS_CHECK_HIP(g.err);
+    UPS_CHECK_HIP(hipDeviceSynchronize());
+    if (act_h)
+        UPS_CHECK_HIP(hipMemcpy(act_h, p->act + p->act_off[layer], count * sizeof(uint16_t), hipMemcpyDeviceToHost));
+    if (dact_h)
+        UPS_CHECK_HIP(hipMemcpy(dact_h, p->dact + p->dact_off[layer], count * sizeof(float), hipMemcpyDeviceToHost));
+    return UPS_OK;
+}
+
 ups_status ups_proposal_get_grads(ups_proposal *p, float *grads_h, int64_t n) {
     UPS_REQUIRE(p && grads_h, "null argument");
     UPS_REQUIRE(n == layout().total, "parameter count mismatch");

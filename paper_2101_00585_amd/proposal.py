@@ -224,20 +224,37 @@ def init_params(seed=0):
     return p
 
 
-def train(prop, x, y, steps=6000, batch=256, lr=1e-3, seed=1, val=None, log=None, every=500):
+def _loop_state_path(checkpoint):
+    return checkpoint + ".loop.npz"
+
+
+def train(prop, x, y, steps=6000, batch=256, lr=1e-3, seed=1, val=None, log=None, every=500, checkpoint=None,
+          checkpoint_every=1000, resume=False, until=None):
     """Adam on augmented batches drawn from (x, y); cosine-decayed learning
     rate after a short warm-up.  val = {name: (x_val, y_val)} for periodic
-    error reports.  Returns the loss history."""
+    error reports.  With ``checkpoint`` (a path), every ``checkpoint_every``
+    steps the network's checkpoint (parameters, Adam moments and step count)
+    goes to that path and the loop's state (the next step and the batch
+    generator's state) beside it; ``resume`` continues from them, taking the
+    same batches and learning rates as the uninterrupted run.  ``until``
+    stops before that step (the schedule still spans ``steps``).  Returns the
+    loss history (of this call)."""
     torch = _torch()
     dev = x.device
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
+    start = 0
+    if resume:
+        prop.load_checkpoint(checkpoint)
+        st = np.load(_loop_state_path(checkpoint))
+        start = int(st["step"])
+        gen.set_state(torch.from_numpy(st["rng"]))
     yt = torch.from_numpy(np.asarray(y, dtype=np.float64)).to(dev)
     n = x.shape[0]
     losses = []
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     t0 = time.perf_counter()
-    for s in range(steps):
+    for s in range(start, steps if until is None else min(until, steps)):
         idx = torch.randint(0, n, (batch,), device=dev, generator=gen)
         k = torch.randint(0, COLS, (batch,), device=dev, generator=gen)
         k2 = torch.randint(-SCAN_ROLL, SCAN_ROLL + 1, (batch,), device=dev, generator=gen)
@@ -247,6 +264,9 @@ def train(prop, x, y, steps=6000, batch=256, lr=1e-3, seed=1, val=None, log=None
         warm = min(1.0, (s + 1) / 200.0)
         cur = lr * warm * (0.01 + 0.99 * 0.5 * (1 + math.cos(math.pi * s / steps)))
         prop.train_step(xb, yb, cur, loss)
+        if checkpoint and (s + 1) % checkpoint_every == 0:
+            prop.save_checkpoint(checkpoint)
+            np.savez(_loop_state_path(checkpoint), step=np.int64(s + 1), rng=gen.get_state().numpy())
         if (s + 1) % 50 == 0:
             losses.append((s + 1, float(loss.item())))
         if log and ((s + 1) % every == 0 or s + 1 == steps):
@@ -385,6 +405,8 @@ def main(argv=None):
     ap.add_argument("--log-json", default=None)
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes that render training pairs")
+    ap.add_argument("--checkpoint", default=None, help="training checkpoint path (written every 1000 steps)")
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
     a = ap.parse_args(argv)
 
     def log(m):
@@ -420,7 +442,8 @@ def main(argv=None):
     val = {"val": (xv, yv), "val wide yaw": (xw, yw)}
     prop.set_params(init_params(a.seed))
     t0 = time.perf_counter()
-    losses = train(prop, x, y, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed + 1, val=val, log=log)
+    losses = train(prop, x, y, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed + 1, val=val, log=log,
+                   checkpoint=a.checkpoint, resume=a.resume)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     ev = {name: evaluate(prop, *v) for name, v in val.items()}

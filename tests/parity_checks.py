@@ -154,3 +154,46 @@ def assert_fusion_close(kg_gpu, cnt_gpu, kf_orc, cnt_orc, amb, dr_tol=1e-5, dn_t
     diff |= both & ((rel > dr_tol) | (dn > dn_tol))
     unexplained = diff & ~amb
     return int(diff.sum()), int(amb.sum()), int(unexplained.sum())
+
+
+def association_ambiguous(g, scan, kg, kf, T, d_max, cos_t, eps_px=1e-3, eps=1e-5, eps_dist=1e-4):
+    """Scan pixels whose Omega-inlier decision at pose T (Section III-B) may
+    differ between FP32 and FP64: the point projects within eps_px of a
+    keyframe pixel boundary, the distance is within eps_dist (metres; FP32
+    points at 50 m carry about 1e-5 m of rounding) or the normal gate value
+    within eps of its threshold.  Returns the boolean mask (FP64, numpy
+    only)."""
+    R, t = T[:3, :3], T[:3, 3]
+    ok = _surfel_ok(g, scan)
+    q = (scan[..., 3:4] * _rays(g)) @ R.T + t
+    m = scan[..., :3] @ R.T
+    fi, fj = _proj(kg, q)
+    near = _near_half(fi, eps_px) | _near_half(fj, eps_px)
+    ki = np.floor(fi + 0.5).astype(np.int64)
+    kj = np.floor(fj + 0.5).astype(np.int64) % kg.cols
+    inrow = (ki >= 0) & (ki < kg.rows)
+    kic = np.clip(ki, 0, kg.rows - 1)
+    s1 = kf[kic, kj]
+    x1 = s1[..., 3:4] * _rays(kg)[kic, kj]
+    dist = np.linalg.norm(q - x1, axis=-1)
+    cm = (m * s1[..., :3]).sum(-1)
+    gate = inrow & _surfel_ok(kg, s1) & ((np.abs(dist - d_max) < eps_dist) | (np.abs(cm - cos_t) < eps))
+    return ok & (near | gate)
+
+
+def assert_scores_match(scores, ref, amb):
+    """Integer candidate scores against the oracle's counts: each within its
+    count of ambiguous pixels; the winner (the first maximum) is a candidate
+    that the counts allow to be the maximum, and it is the oracle's own
+    winner wherever the oracle's margin exceeds the ambiguity."""
+    scores, ref, amb = np.asarray(scores), np.asarray(ref), np.asarray(amb)
+    dev = np.abs(scores - ref)
+    assert (dev <= amb).all(), (int(dev.max()), int(amb[np.argmax(dev - amb)]))
+    c = int(np.argmax(scores))
+    lo, hi = ref - amb, ref + amb
+    assert hi[c] >= lo.max(), (c, hi[c], lo.max())
+    c_ref = int(np.argmax(ref))
+    others = np.delete(hi, c_ref)
+    if others.size == 0 or lo[c_ref] > others.max():
+        assert c == c_ref, (c, c_ref)
+    return int(dev.sum()), int(amb.sum())

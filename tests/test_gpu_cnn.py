@@ -127,33 +127,146 @@ def prop(gpu_lib):
     ctx.close()
 
 
-def test_network_forward(gpu_lib, prop):
+EPS32 = 2.0 ** -24
+
+
+def _bf16_flip_band(z, err):
+    """Elements whose bfloat16-rounded ReLU output may differ between the
+    pre-activation z and a value within err of it: |z| <= err (zero or not),
+    or z > err within err of a bf16 rounding boundary."""
+    b = C.bf16_round(z)
+    e = np.floor(np.log2(np.maximum(np.abs(b), 1e-38)))
+    half_ulp = 2.0 ** (e - 8)
+    return (np.abs(z) <= err) | ((z > err) & (half_ulp - np.abs(z - b) <= err))
+
+
+def test_network_forward_layer_by_layer(gpu_lib, prop):
+    """The network object's forward pass, layer by layer on identical inputs:
+    the oracle's convolution of the GPU's stored bfloat16 input of each layer
+    (FP64) rounded to bfloat16 equals the GPU's stored output, except where
+    the FP32 accumulation (at most K 2^-24 sum |x w| for K terms) can move the
+    value across a bfloat16 rounding boundary, and there it is one bfloat16
+    step away; the FP32 head equals the oracle's on the GPU's features within
+    its accumulation bound."""
     p = _params(1)
     x = _inputs(2, 5)
     prop.set_params(p)
     y = _np(prop.forward(5, _bf(x)))
-    ref = C.forward(p, x, bf16=True)
-    assert np.abs(y - ref).max() <= 1e-2 * (np.abs(ref).max() + 1.0), (y, ref)
+    convs, (Wfc, bfc) = C.unflatten(p)
+    a = x
+    for k, ((W, b), (cin, cout, s)) in enumerate(zip(convs, C.LAYERS)):
+        got, _ = prop.activations(k + 1, 5)
+        Wb = C.bf16_round(W)
+        z = C.conv_forward(a, Wb, b, s)
+        bound = 9 * cin * EPS32 * (C.conv_forward(np.abs(a), np.abs(Wb), np.abs(b), s) + 1e-30)
+        ref = C.bf16_round(C.relu(z))
+        band = _bf16_flip_band(z, bound)
+        diff = got != ref
+        print(f"layer {k + 1}: {diff.sum()} of {diff.size} outputs differ, {band.sum()} in the rounding band")
+        assert not (diff & ~band).any(), (k, int((diff & ~band).sum()))
+        assert (np.abs(got - ref)[diff] <= 2.0 ** (np.floor(np.log2(np.maximum(np.abs(ref[diff]), 1e-38))) - 7)
+                + bound[diff]).all()
+        assert band.mean() < 0.5  # at least half the outputs are held bit-exact
+        a = got
+    f = a.reshape(a.shape[0], -1)
+    y_ref = C.fc_forward(f, Wfc, bfc)
+    bound = C.FEAT * EPS32 * (np.abs(f) @ np.abs(Wfc).T + np.abs(bfc)) + 1e-30
+    assert (np.abs(y - y_ref) <= bound).all(), np.abs(y - y_ref).max()
 
 
-def test_network_gradients(gpu_lib, prop):
+def _within(got, ref, floor, rel=1e-4):
+    return np.abs(got - ref) <= rel * np.abs(ref) + floor
+
+
+def test_network_gradients_layer_by_layer(gpu_lib, prop):
+    """One training step (lr = 0) checked stage by stage on identical
+    inputs: the loss, the head's gradients and the feature gradient from the
+    GPU's output and features; each convolution's weight and bias gradients
+    and its input gradient from the GPU's stored input, output and output
+    gradient of that layer.  Both backward passes take the masked output
+    gradient as a bfloat16 matrix-core operand, so the oracle is fed the same
+    bfloat16 values and only accumulation differs.  Element-wise: within 1e-4
+    relative plus the FP32 accumulation bound n 2^-24 sum |terms| of the
+    element's own n terms."""
     import torch
     p = _params(3)
     x = _inputs(4, 6)
     target = _rng(5).normal(size=(6, 6))
     prop.set_params(p)
+    y = _np(prop.forward(6, _bf(x))).astype(np.float64)
     loss = prop.train_step(_bf(x), _f32(target), lr=0.0)
     torch.cuda.synchronize()
     g = prop.get_grads().astype(np.float64)
-    L, gref = C.gradients(p, x, target, bf16=True)
-    assert abs(float(loss.item()) - L) <= 1e-3 * abs(L)
-    # parameters unchanged at lr = 0
     assert np.array_equal(prop.get_params(), p.astype(np.float32))
-    sizes = np.cumsum([0] + C.param_sizes())
-    for k in range(len(sizes) - 1):
-        a, b = g[sizes[k]:sizes[k + 1]], gref[sizes[k]:sizes[k + 1]]
-        rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
-        assert rel < 2e-2, (k, rel)
+    convs, (Wfc, bfc) = C.unflatten(p)
+    gconvs, (gWfc, gbfc) = C.unflatten(g)
+    acts = [x] + [prop.activations(k, 6)[0] for k in range(1, 6)]
+    dacts = [None] + [prop.activations(k, 6)[1] for k in range(1, 6)]
+    L = C.loss(y, target)
+    assert abs(float(loss.item()) - L) <= 1e-5 * abs(L)
+    # head
+    dout = C.loss_grad(y, target)
+    f = acts[5].reshape(6, -1)
+    df, dW, db = C.fc_backward(f, Wfc, dout)
+    adf, adW, adb = C.fc_backward(np.abs(f), np.abs(Wfc), np.abs(dout))
+    assert _within(gWfc, dW, 6 * EPS32 * adW + 1e-30).all()
+    assert _within(gbfc, db, 6 * EPS32 * adb + 1e-30).all()
+    assert _within(dacts[5].reshape(6, -1), df, 6 * EPS32 * adf + 1e-30).all()
+    # convolutions, last to first
+    checked = 0
+    for k in range(4, -1, -1):
+        cin, cout, s = C.LAYERS[k]
+        Wb = C.bf16_round(convs[k][0])
+        xk, yk, dyk = acts[k], acts[k + 1], C.bf16_round(dacts[k + 1])
+        dx, dW, db = C.conv_backward(xk, yk, dyk, Wb, s)
+        adx, adW, adb = C.conv_backward(np.abs(xk), yk, np.abs(dyk), np.abs(Wb), s)
+        m = yk.shape[0] * yk.shape[1] * yk.shape[2]  # terms of a weight-gradient element
+        ok_w = _within(gconvs[k][0], dW, m * EPS32 * adW + 1e-30)
+        ok_b = _within(gconvs[k][1], db, m * EPS32 * adb + 1e-30)
+        print(f"layer {k + 1}: weight gradient max rel err "
+              f"{(np.abs(gconvs[k][0] - dW) / (np.abs(dW) + 1e-30)).max():.2e}")
+        assert ok_w.all() and ok_b.all(), (k, int((~ok_w).sum()), int((~ok_b).sum()))
+        if k > 0:
+            ok_x = _within(dacts[k], dx, 9 * cout * EPS32 * adx + 1e-30)
+            assert ok_x.all(), (k, int((~ok_x).sum()))
+        checked += dW.size
+    assert checked == sum(9 * ci * co for ci, co, _ in C.LAYERS)
+
+
+def test_checkpoint_resumes_training_exactly(gpu_lib, prop, tmp_path):
+    """Two Adam steps, a checkpoint, a third step; a new network loaded from
+    the checkpoint takes the third step to bitwise the same parameters, while
+    one loaded from the parameter file alone (moments reset) does not."""
+    import torch
+    p = _params(13) * 0.5
+    xa, xb = _bf(_inputs(14, 8)), _bf(_inputs(15, 8))
+    ta, tb = _f32(_rng(16).normal(size=(8, 6))), _f32(_rng(17).normal(size=(8, 6)))
+    prop.set_params(p)
+    prop.train_step(xa, ta, lr=1e-3)
+    prop.train_step(xb, tb, lr=1e-3)
+    ckpt, params_file = str(tmp_path / "state.ckpt"), str(tmp_path / "params.bin")
+    prop.save_checkpoint(ckpt)
+    prop.save(params_file)
+    prop.train_step(xa, ta, lr=1e-3)
+    torch.cuda.synchronize()
+    want = prop.get_params()
+    raw = open(ckpt, "rb").read()
+    assert raw[:8] == b"UPSCKP01" and int.from_bytes(raw[16:24], "little") == 2
+    for loader, same in (("load_checkpoint", True), ("load", False)):
+        other = gpu_lib.Proposal(prop.ctx, 8)
+        try:
+            getattr(other, loader)(ckpt if same else params_file)
+            other.train_step(xa, ta, lr=1e-3)
+            torch.cuda.synchronize()
+            assert np.array_equal(other.get_params(), want) == same, loader
+        finally:
+            other.close()
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(raw[:-4])
+    with pytest.raises(gpu_lib.UpsError):
+        prop.load_checkpoint(str(bad))
+    with pytest.raises(gpu_lib.UpsError):
+        prop.load_checkpoint(params_file)
 
 
 def test_adam_steps(gpu_lib, prop):
@@ -250,5 +363,31 @@ def test_parameter_file_round_trip(gpu_lib, prop, tmp_path):
         with pytest.raises(gpu_lib.UpsError):
             other.load(str(bad))
         assert np.array_equal(other.get_params(), ref)
+    finally:
+        other.close()
+
+
+def test_training_loop_resumes_exactly(gpu_lib, prop, tmp_path):
+    """The training loop interrupted after 3 of 6 steps and resumed from its
+    checkpoint (parameters, Adam moments, step count, the batch generator's
+    state) ends with bitwise the parameters of the uninterrupted run."""
+    import torch
+    from paper_2101_00585_amd import proposal as P
+    x = _bf(_inputs(20, 12))
+    y = _rng(21).normal(size=(12, 6)) * 0.3
+    p0 = _params(22) * 0.5
+    ck = str(tmp_path / "loop.ckpt")
+    prop.set_params(p0)
+    P.train(prop, x, y, steps=6, batch=4, lr=1e-3, seed=7)
+    torch.cuda.synchronize()
+    want = prop.get_params()
+    prop.set_params(p0)
+    P.train(prop, x, y, steps=6, batch=4, lr=1e-3, seed=7, checkpoint=ck, checkpoint_every=3, until=3)
+    other = gpu_lib.Proposal(prop.ctx, 8)
+    try:
+        other.set_params(np.zeros_like(p0))
+        P.train(other, x, y, steps=6, batch=4, lr=1e-3, seed=99, checkpoint=ck, resume=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(other.get_params(), want)
     finally:
         other.close()

@@ -98,7 +98,9 @@ def test_normals_exact_plane(gpu_lib, ctx):
                                      params=gpu_lib.NormalParams(atrous_levels=2, max_rel_jump=1e9)))
     m = _normal_mask(s)
     assert m.sum() > 5000
-    assert np.abs(s[m][:, :3] + n).max() < 1e-4
+    err = np.linalg.norm(s[m][:, :3] + n, axis=-1)
+    print(f"exact plane: normal error max {err.max():.2e}, median {np.median(err):.2e} over {m.sum()} pixels")
+    assert err.max() < 1e-5
 
 
 def test_normals_invalid_inputs(gpu_lib, ctx, c0):
