@@ -114,25 +114,14 @@ def cpu_info():
     return model, os.cpu_count()
 
 
-def _oracle_surfel(args):
-    import oracle as O
-    g, depth = args
-    return O.panorama_normals(g, depth)
-
-
 def cpu_baseline(c1, budget_s):
     """FP64 oracle, one thread: normals of the scan + 3-level registration +
     fusion, repeated until about budget_s seconds of work."""
-    import concurrent.futures
-    import multiprocessing as mp
-
     import oracle as O
     g = c1["geom"]
-    # keyframe (setup, untimed): oracle normals of the 10 keyframe scans in
-    # worker processes, then oracle fusion in order
-    with concurrent.futures.ProcessPoolExecutor(max_workers=min(10, os.cpu_count() or 1),
-                                                mp_context=mp.get_context("spawn")) as ex:
-        surf = list(ex.map(_oracle_surfel, [(g, d) for d in c1["kf_scans"]]))
+    # keyframe (setup, untimed; about 2 s): oracle normals of the 10 keyframe
+    # scans, then oracle fusion in order
+    surf = [O.panorama_normals(g, d) for d in c1["kf_scans"]]
     kf = np.zeros((g.rows, g.cols, 4))
     cnt = np.zeros((g.rows, g.cols), np.uint16)
     for s, T in zip(surf, c1["T_kf_scans"]):
