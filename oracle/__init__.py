@@ -34,11 +34,30 @@ _LIB = None
 STATUS = {0: "CONVERGED", 1: "MAX_ITERS", 2: "DEGENERATE", 3: "NO_INLIERS", 4: "FALLBACK_USED"}
 
 
-def build() -> str:
-    so = os.path.join(_HERE, "liboracle.so")
+# UPS_SANITIZE=1 selects a build instrumented with AddressSanitizer and
+# UBSan (clang; its runtime must be preloaded into the process, see
+# tests/run_cpu_sanitized.sh)
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined", "-shared-libsan"]
+
+
+def sanitized() -> bool:
+    return os.environ.get("UPS_SANITIZE") == "1"
+
+
+def _so_path(sanitize):
+    return os.path.join(_HERE, "liboracle_san.so" if sanitize else "liboracle.so")
+
+
+def build(sanitize: bool | None = None) -> str:
+    sanitize = sanitized() if sanitize is None else sanitize
+    so = _so_path(sanitize)
     tmp = so + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-std=c11", "-O2", "-fno-fast-math", "-fPIC", "-shared", "-o", tmp,
-                           os.path.join(_HERE, "orc.c"), "-lm"])
+    if sanitize:
+        cmd = ["/opt/rocm/llvm/bin/clang", "-std=c11", *SANITIZE_FLAGS]
+    else:
+        cmd = ["gcc", "-std=c11", "-O2"]
+    subprocess.check_call(cmd + ["-fno-fast-math", "-fPIC", "-shared", "-o", tmp, os.path.join(_HERE, "orc.c"), "-lm"])
     os.replace(tmp, so)
     return so
 
@@ -46,7 +65,7 @@ def build() -> str:
 def _lib():
     global _LIB
     if _LIB is None:
-        so = os.path.join(_HERE, "liboracle.so")
+        so = _so_path(sanitized())
         srcs = [os.path.join(_HERE, f) for f in ("orc.c", "orc.h")]
         if not os.path.exists(so) or os.path.getmtime(so) < max(os.path.getmtime(s) for s in srcs):
             build()

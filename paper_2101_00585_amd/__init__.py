@@ -22,7 +22,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libupslam.so")
+# UPS_SANITIZE=1 loads the build whose host code carries AddressSanitizer and
+# UBSan (python -m paper_2101_00585_amd.build --sanitize)
+_SO = os.path.join(_HERE, "libupslam_san.so" if os.environ.get("UPS_SANITIZE") == "1" else "libupslam.so")
 _LIB = None
 
 STATUS = {0: "CONVERGED", 1: "MAX_ITERS", 2: "DEGENERATE", 3: "NO_INLIERS", 4: "FALLBACK_USED"}

@@ -29,15 +29,24 @@ def _hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
+# Host code only, instrumented with AddressSanitizer and UBSan (device code
+# is built as usual); the sanitizers' runtime is preloaded into the process
+# that loads the library (tests/run_cpu_sanitized.sh).
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+                 "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+SO_SANITIZED = os.path.join(HERE, "libupslam_san.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
+    flags = FLAGS + (HOST_SANITIZE if sanitize else [])
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc, *FLAGS, "-c", src, "-o", obj]
+        cmd = [hipcc, *flags, "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
         if r.returncode != 0:
@@ -48,14 +57,20 @@ def build(verbose: bool = False) -> str:
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    so = SO_SANITIZED if sanitize else SO
+    tmp = so + ".tmp%d" % os.getpid()
+    if sanitize:
+        # the objects already hold their device code: a host link against the HIP runtime
+        cmd = ["/opt/rocm/llvm/bin/clang++", "-shared", "-fPIC", "-fsanitize=address,undefined", "-shared-libsan",
+               "-o", tmp, *objs, "-L/opt/rocm/lib", "-lamdhip64"]
+    else:
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, SO)
-    return SO
+    os.replace(tmp, so)
+    return so
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -35,10 +35,20 @@ _LIB = None
 DEFAULT_THREADS = None
 
 
+def _sanitized() -> bool:
+    # UPS_SANITIZE=1: a build instrumented with AddressSanitizer and UBSan
+    # (clang; its runtime preloaded into the process)
+    return os.environ.get("UPS_SANITIZE") == "1"
+
+
+def _so_path(sanitize):
+    return os.path.join(_HERE, "libsynth_san.so" if sanitize else "libsynth.so")
+
+
 def _lib():
     global _LIB
     if _LIB is None:
-        so = os.path.join(_HERE, "libsynth.so")
+        so = _so_path(_sanitized())
         src = os.path.join(_HERE, "render.c")
         if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
             build()
@@ -47,12 +57,19 @@ def _lib():
     return _LIB
 
 
-def build() -> str:
-    """Compile the ray caster with gcc (plain C, no fast-math)."""
-    so = os.path.join(_HERE, "libsynth.so")
+def build(sanitize=None) -> str:
+    """Compile the ray caster with gcc (plain C, no fast-math), or with clang
+    and the sanitizers."""
+    sanitize = _sanitized() if sanitize is None else sanitize
+    so = _so_path(sanitize)
     tmp = so + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-fPIC", "-shared", "-o", tmp,
-                           os.path.join(_HERE, "render.c"), "-lm", "-lpthread"])
+    if sanitize:
+        cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined", "-shared-libsan"]
+    else:
+        cmd = ["gcc", "-O2"]
+    subprocess.check_call(cmd + ["-fno-fast-math", "-fPIC", "-shared", "-o", tmp, os.path.join(_HERE, "render.c"),
+                                 "-lm", "-lpthread"])
     os.replace(tmp, so)
     return so
 

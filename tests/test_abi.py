@@ -9,7 +9,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "upslam.h")
-SO = os.path.join(ROOT, "paper_2101_00585_amd", "libupslam.so")
+SO = os.path.join(ROOT, "paper_2101_00585_amd",
+                  "libupslam_san.so" if os.environ.get("UPS_SANITIZE") == "1" else "libupslam.so")
 
 
 def _declared():
@@ -22,7 +23,7 @@ def _declared():
 def lib():
     if not os.path.exists(SO):
         from paper_2101_00585_amd import build
-        build.build()
+        build.build(sanitize=os.environ.get("UPS_SANITIZE") == "1")
     return ctypes.CDLL(SO)
 
 
