@@ -174,6 +174,14 @@ void ups_context_destroy(ups_context *ctx);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char *ups_last_error(void);
 
+/* Debug (determinism checks, Section III-B reductions): with reversed != 0,
+ * every registration iteration / evaluation launch enqueued afterwards, in any
+ * thread, deals its tiles to workgroups in the reverse of the usual order.
+ * Block partials are reduced in tile order, so results are bitwise the same
+ * either way.  Process-wide; launches already enqueued or captured keep the
+ * order they were enqueued with.  Always UPS_OK. */
+ups_status ups_debug_reverse_tile_order(int32_t reversed);
+
 /* Surfel image (Section III-A) from a range image.  depth_d: float[rows][cols];
  * surfel_d: float[rows][cols][4] output (must not alias depth_d). */
 ups_status ups_panorama_normals(ups_context *ctx, const ups_geom *g, const float *depth_d, float *surfel_d,
@@ -329,10 +337,19 @@ ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const 
 /* ------------------------------------------------------------------------
  * Batches: many independent registrations of uneven panorama sizes (e.g. the
  * candidate transforms of a loop-closure search, Section III-C) advanced
- * together.  One launch per Gauss-Newton iteration covers every registration
- * of the batch; a registration that met its stop criterion or failed drops out
- * of the remaining launches.  The launch sequence is fixed at planning time,
- * so a whole ups_register_batch call can be captured in a HIP graph.
+ * together.  Two schedulers, chosen per batch (ups_batch_set_scheduler):
+ *   UPS_SCHED_LAUNCHES (default): one launch per Gauss-Newton iteration covers
+ *     every registration of the batch, one small launch per iteration solves
+ *     and updates them; a registration that met its stop criterion or failed
+ *     drops out of the remaining launches (its blocks exit at once).
+ *   UPS_SCHED_PERSISTENT: one persistent launch in which each registration
+ *     advances through its iterations as its own chain of jobs (the tiles of
+ *     an iteration, then the update by the block that finishes the last
+ *     tile), so the launch's work follows the active registrations.
+ * Both end with one evaluation launch over all registrations at their final
+ * poses and one finish launch, give the same results (the same fixed-order
+ * sums), and are fixed at planning time, so a whole ups_register_batch call
+ * can be captured in a HIP graph.
  * ------------------------------------------------------------------------ */
 
 /* One registration of a batch.  scan_surfel_d / kf_surfel_d are the surfel
@@ -427,6 +444,21 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
 
 /* Pixels per thread the batch launches use at each pyramid level. */
 ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]);
+
+enum {
+    UPS_SCHED_LAUNCHES = 0,   /* one launch per iteration (default) */
+    UPS_SCHED_PERSISTENT = 1  /* one persistent launch, per-registration job chains */
+};
+
+/* Choose the scheduler of later ups_register_batch / fallback calls on this
+ * batch (UPS_SCHED_*; UPS_ERR_INVALID_ARG otherwise).  Host only; takes
+ * effect for calls enqueued afterwards. */
+ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler);
+
+/* The persistent launch of UPS_SCHED_PERSISTENT: its blocks (the kernel's
+ * resident blocks on the device), and the pixels per thread of a tile at each
+ * pyramid level. */
+ups_status ups_batch_schedule(const ups_batch *b, int32_t *blocks, int32_t kpt[4]);
 
 /* ------------------------------------------------------------------------
  * Learned pose proposal.  The paper starts loop-closure registrations from a

@@ -120,6 +120,9 @@ def load():
         "ups_batch_fallback_run": [_P, _P, _P, _P],
         "ups_batch_grid_search": [_P, _P, _P, _P, _P, _P, _P, _P],
         "ups_batch_pixels_per_thread": [_P, _P],
+        "ups_batch_schedule": [_P, _P, _P],
+        "ups_batch_set_scheduler": [_P, ctypes.c_int32],
+        "ups_debug_reverse_tile_order": [ctypes.c_int32],
         "ups_splat_sweep": [_P, _P, _P, _P, _P, _P, _P],
         "ups_keyframe_consistency": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_classify_loop_closures": [_P, ctypes.c_int32, _P, ctypes.c_double, _P, _P, _P],
@@ -560,6 +563,12 @@ def normal_equations(ctx: Context, scan_geom, scan_surfel, kf_geom, kf_surfel, T
     return out
 
 
+def debug_reverse_tile_order(reversed_: bool):
+    """Debug: later registration launches deal their tiles to workgroups in
+    reverse order (results must not change)."""
+    _check(_LIB.ups_debug_reverse_tile_order(1 if reversed_ else 0))
+
+
 # ----------------------------------------------------------------------------
 # batches
 # ----------------------------------------------------------------------------
@@ -669,6 +678,18 @@ class Batch:
                                           _dev_ptr(best_score, torch.int32, "best scores"), _stream()))
         self._grid_keep = base
         return best, best_score, scores
+
+    def set_scheduler(self, persistent):
+        """Run later register calls as one launch per iteration (False, the
+        default) or as one persistent launch (True)."""
+        _check(_LIB.ups_batch_set_scheduler(self._h, 1 if persistent else 0))
+
+    def schedule(self):
+        """(blocks of the persistent launch, pixels per thread of a tile per level)."""
+        blocks = ctypes.c_int32()
+        kpt = (ctypes.c_int32 * 4)()
+        _check(_LIB.ups_batch_schedule(self._h, ctypes.byref(blocks), kpt))
+        return blocks.value, list(kpt)
 
     def pixels_per_thread(self):
         out = (ctypes.c_int32 * 4)()

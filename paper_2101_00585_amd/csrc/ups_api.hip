@@ -1,6 +1,7 @@
 // C ABI entry points (include/upslam.h): argument validation, the context
 // with all device scratch memory, the per-geometry ray tables, and dispatch to
 // the kernel launchers.
+#include <atomic>
 #include <cmath>
 #include <string>
 
@@ -9,6 +10,7 @@
 namespace ups {
 
 static thread_local std::string g_last_error;
+static std::atomic<int> g_reverse_tiles{0};
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
@@ -128,9 +130,18 @@ ups_status check_levels(const ups_geom *g, int levels, const char *what) {
 
 using namespace ups;
 
+namespace ups {
+bool debug_reverse_tiles() { return g_reverse_tiles.load(std::memory_order_relaxed) != 0; }
+}  // namespace ups
+
 extern "C" {
 
 const char *ups_last_error(void) { return g_last_error.c_str(); }
+
+ups_status ups_debug_reverse_tile_order(int32_t reversed) {
+    g_reverse_tiles.store(reversed ? 1 : 0, std::memory_order_relaxed);
+    return UPS_OK;
+}
 
 ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels, int32_t max_batch,
                               int64_t max_batch_pixels) {

@@ -2,12 +2,19 @@
 //
 // Planning (ups_batch_create) lays out every registration's descriptor, its
 // pyramid levels, two state slots and two partial buffers in device memory,
-// plus one prefix table of tile counts per pyramid level.  Running
-// (ups_register_batch) is a fixed launch sequence: one prepare launch (states
-// and pyramids of all registrations), one launch per Gauss-Newton iteration
-// covering the tiles of every registration at that level, one evaluation
-// launch and one finish launch (a block per registration).  Registrations
-// whose level converged or that failed leave their tiles idle.
+// plus one prefix table of tile counts per pyramid level and the persistent
+// scheduler's ticket map.  A call (ups_register_batch) starts with one prepare
+// launch (states and pyramids of all registrations), then runs the
+// Gauss-Newton iterations under one of two schedulers:
+//   launches: per iteration one launch over every tile of the level (blocks of
+//     registrations that stopped exit at once) and one solve launch;
+//   persistent: the scheduler's set-up (the first job of every registration)
+//     and one persistent launch in which every registration advances through
+//     its iterations independently of the others (k_icp_persistent; a
+//     registration whose level converged or that failed publishes no further
+//     iterations, so the launch's work follows the active registrations);
+// and ends with the evaluation launch at the final poses and the finish
+// launch that writes the results.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -42,6 +49,16 @@ struct ups_batch {
     Compact *comp = nullptr;         // the registrations the fallback reruns ...
     int *comp_list = nullptr;        // ... [n]
     int *comp_start = nullptr;       // ... and their tile prefix tables [4][n+1]
+    int scheduler = UPS_SCHED_LAUNCHES;
+    // persistent scheduler
+    int Kp = 0;                       // the persistent kernel's pixels per thread (the largest of kpt)
+    int kpt[4] = {1, 1, 1, 1};        // pixels per thread of its tiles at each level
+    int grid = 0;                     // its resident blocks
+    int map_size = 0;                 // tickets of a call, at most
+    Sched *sched = nullptr;
+    unsigned long long *tile_map = nullptr;  // [map_size]
+    SchedJob *jobs = nullptr;                // [n]
+    int *arrived = nullptr;                  // [n]
 };
 
 // Grid of the launches over a subset of the batch (the fallback): they stride
@@ -65,6 +82,10 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->mask);
     (void)hipFree(b->alt);
     (void)hipFree(b->comp);
+    (void)hipFree(b->sched);
+    (void)hipFree(b->tile_map);
+    (void)hipFree(b->jobs);
+    (void)hipFree(b->arrived);
     delete b;
 }
 
@@ -86,13 +107,10 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     UPS_REQUIRE(n >= 1 && n <= ctx->max_batch, "n must be in [1, the context's max_batch]");
     UPS_REQUIRE(pixels_per_thread == 0 || (pixels_per_thread <= 64 && (pixels_per_thread & (pixels_per_thread - 1)) == 0),
                 "pixels_per_thread must be 0 or a power of two up to 64");
-    UPS_REQUIRE(p->levels >= 1 && p->levels <= 4, "levels must be in [1, 4]");
-    for (int l = 0; l < p->levels; l++) {
-        UPS_REQUIRE(p->iters[l] >= 0 && p->iters[l] <= 1000, "iters must be in [0, 1000]");
-        UPS_REQUIRE(p->d_max[l] > 0.f, "d_max must be > 0");
+    {
+        const ups_status pst = check_icp_params(p);
+        if (pst != UPS_OK) return pst;
     }
-    UPS_REQUIRE(p->precision >= UPS_PREC_KAHAN_F64 && p->precision <= UPS_PREC_F64, "unknown precision mode");
-    UPS_REQUIRE(p->stop_update_norm >= 0.0, "stop_update_norm must be >= 0");
     DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     const int L = p->levels, s = 1 << (L - 1);
@@ -128,6 +146,17 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
             return UPS_ERR_INVALID_ARG;
         }
         b->K[l] = K;
+    }
+    // the persistent kernel is compiled for the largest of these and tiles
+    // each level with its own (at least a pixel group of the kernel, 4), so
+    // no level has more tiles than the partial buffers hold
+    for (int l = 0; l < L; l++) b->Kp = std::max(b->Kp, b->K[l]);
+    for (int l = 0; l < L; l++) b->kpt[l] = std::max(b->K[l], std::min(b->Kp, 4));
+    b->grid = persistent_grid(b->Kp, p->precision, p->irls_delta > 0.f);
+    if (b->grid < 1) {
+        free_batch(b);
+        set_error("no resident blocks for the persistent batch kernel");
+        return UPS_ERR_HIP;
     }
 
     // host descriptors
@@ -165,6 +194,24 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         b->total_tiles[l] = tile_start[l * (n + 1) + n];
     }
     b->total_pre = pre_start[n];
+    // tickets of a call, at most: every iteration of every level of every
+    // registration, plus the last ticket of each block
+    {
+        int64_t tickets = b->grid + 64;
+        for (int k = 0; k < n; k++) {
+            for (int l = 0; l < L; l++) {
+                const int64_t np = (int64_t)hi[k].sg[l].rows * hi[k].sg[l].cols;
+                const int64_t t = (np + kBlock * b->kpt[l] - 1) / (kBlock * b->kpt[l]);
+                tickets += t * p->iters[l];
+            }
+        }
+        if (tickets > (int64_t)1 << 30) {
+            free_batch(b);
+            set_error("batch too large for the scheduler's ticket map");
+            return UPS_ERR_INVALID_ARG;
+        }
+        b->map_size = (int)tickets;
+    }
 
     // batched-normals images: every scan / keyframe with a depth pointer
     std::vector<NormImg> nimg;
@@ -197,6 +244,10 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->mask, (size_t)n);
     alloc((void **)&b->alt, (size_t)n * sizeof(ups_icp_result));
     alloc((void **)&b->comp, sizeof(Compact) + ((size_t)n + 4 * ((size_t)n + 1)) * sizeof(int) + 64);
+    alloc((void **)&b->sched, sizeof(Sched));
+    alloc((void **)&b->tile_map, (size_t)b->map_size * sizeof(unsigned long long));
+    alloc((void **)&b->jobs, (size_t)n * sizeof(SchedJob));
+    alloc((void **)&b->arrived, (size_t)n * sizeof(int));
     if (e == hipSuccess) {
         b->comp_list = (int *)((char *)b->comp + 64);
         b->comp_start = b->comp_list + n;
@@ -250,6 +301,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     if (e == hipSuccess)
         e = hipMemcpy(b->d_pre_start, pre_start.data(), pre_start.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->state, 0, (size_t)n * 2 * sizeof(RegState));
+    if (e == hipSuccess) e = hipMemset(b->sched, 0, sizeof(Sched));  // epoch 0: no ticket carries a tile yet
+    if (e == hipSuccess) e = hipMemset(b->tile_map, 0, (size_t)b->map_size * sizeof(unsigned long long));
     if (e == hipSuccess && !nimg.empty()) {
         e = hipMemcpy(b->d_nimg, nimg.data(), nimg.size() * sizeof(NormImg), hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -317,6 +370,21 @@ ups_status ups_batch_pixels_per_thread(const ups_batch *b, int32_t out[4]) {
     return UPS_OK;
 }
 
+ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler) {
+    UPS_REQUIRE(b, "null argument");
+    UPS_REQUIRE(scheduler == UPS_SCHED_LAUNCHES || scheduler == UPS_SCHED_PERSISTENT,
+                "scheduler must be UPS_SCHED_LAUNCHES or UPS_SCHED_PERSISTENT");
+    b->scheduler = scheduler;
+    return UPS_OK;
+}
+
+ups_status ups_batch_schedule(const ups_batch *b, int32_t *blocks, int32_t kpt[4]) {
+    UPS_REQUIRE(b && blocks && kpt, "null argument");
+    *blocks = b->grid;
+    for (int l = 0; l < 4; l++) kpt[l] = b->kpt[l];
+    return UPS_OK;
+}
+
 ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_params *p, void *stream) {
     UPS_REQUIRE(ctx && b && p, "null argument");
     UPS_REQUIRE(p->atrous_levels >= 1 && p->atrous_levels <= 3, "batched normals need atrous_levels in [1, 3]");
@@ -334,7 +402,7 @@ namespace {
 // The launch sequence of a batch call; with a mask only the masked-in
 // registrations run (their pyramids left by the previous call are reused),
 // through the batch's Compact list of them.
-ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
+ups_status register_batch_launches(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
                                hipStream_t s) {
     ups_status st;
     const ups_icp_params &p = b->p;
@@ -384,6 +452,65 @@ ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8
         st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0], s);
     if (st != UPS_OK) return st;
     return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
+}
+
+// A batch call under the persistent scheduler: prepare (states, and pyramids
+// unless a mask reuses those of the previous call), the scheduler's first
+// jobs (mask: only the masked-in registrations take part; the others keep
+// their results), the persistent launch that runs every registration through
+// its iterations, the evaluation launch and the finish launch.
+ups_status register_batch_persistent(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
+                               hipStream_t s) {
+    ups_status st;
+    const ups_icp_params &p = b->p;
+    if ((st = launch_prepare_batch(b->d_inst, init_d, b->n, p.levels, b->d_pre_start, b->total_pre, mask, s)) !=
+        UPS_OK)
+        return st;
+    SchedArgs A;
+    memset(&A, 0, sizeof(A));
+    A.sched = b->sched;
+    A.tile_map = b->tile_map;
+    A.jobs = b->jobs;
+    A.arrived = b->arrived;
+    A.insts = b->d_inst;
+    A.results = results_d;
+    A.mask = mask;
+    A.n = b->n;
+    A.map_size = b->map_size;
+    A.levels = p.levels;
+    for (int l = 0; l < 4; l++) A.kpt[l] = b->kpt[l];
+    for (int l = 0; l < 4; l++) {
+        A.iters[l] = l < p.levels ? p.iters[l] : 0;
+        A.d_max2[l] = l < p.levels ? p.d_max[l] * p.d_max[l] : 0.f;
+    }
+    A.cos_theta = p.cos_theta_max;
+    A.irls_delta = p.irls_delta;
+    A.min_inliers = p.min_inliers;
+    A.stop_norm = p.stop_update_norm;
+    if ((st = launch_sched_init(A, s)) != UPS_OK) return st;
+    if ((st = launch_icp_persistent(b->Kp, p.precision, A, b->grid, s)) != UPS_OK) return st;
+    // quality at the final poses: one evaluation launch over every tile of
+    // level 0 (masked-out registrations leave), then one block per result
+    StepArgs e;
+    memset(&e, 0, sizeof(e));
+    e.level = 0;
+    e.prev_level = -1;
+    e.d_max2 = p.d_max[0] * p.d_max[0];
+    e.tau2 = e.d_max2;
+    e.cos_theta = p.cos_theta_max;
+    e.irls_delta = p.irls_delta;
+    e.min_inliers = p.min_inliers;
+    e.stop_norm = p.stop_update_norm;
+    if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, b->n, e, b->total_tiles[0],
+                               s)) != UPS_OK)
+        return st;
+    return launch_finish_batch(p.precision, b->d_inst, b->n, 0, results_d, s);
+}
+
+ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
+                               hipStream_t s) {
+    if (b->scheduler == UPS_SCHED_PERSISTENT) return register_batch_persistent(b, init_d, mask, results_d, s);
+    return register_batch_launches(b, init_d, mask, results_d, s);
 }
 
 }  // namespace

@@ -5,7 +5,9 @@
 
 namespace ups {
 
-enum { MODE_ITER = 0, MODE_EVAL = 1 };
+// MODE_SCHED: an iteration tile of the persistent batch kernel (the
+// iteration sums; state and partial exchanged as agent-coherent words).
+enum { MODE_ITER = 0, MODE_EVAL = 1, MODE_SCHED = 2 };
 
 // Registration state, two ping-pong slots per registration.
 struct RegState {
@@ -46,7 +48,17 @@ struct StepArgs {
     float irls_delta;  // > 0: inlier terms weighted by 1 / max(|r|, irls_delta)
     int min_inliers;
     double stop_norm;
+    int kpt;  // MODE_SCHED: pixels per thread of this tile (<= the kernel's K, a multiple of its pixel groups)
+    int reverse_tiles;  // debug: workgroups take the tiles in reverse order (set by the launchers)
 };
+
+// Debug tile order of the iteration / evaluation launches (ups_debug_reverse_tile_order).
+bool debug_reverse_tiles();
+inline StepArgs with_tile_order(const StepArgs &a) {
+    StepArgs b = a;
+    b.reverse_tiles = debug_reverse_tiles() ? 1 : 0;
+    return b;
+}
 
 // A subset of a batch's registrations: list[m] for m < count, and per level
 // l the prefix table start[l][m] (m <= count) of their tile counts, whose
@@ -54,6 +66,42 @@ struct StepArgs {
 struct Compact {
     int count;
     int total[4];
+};
+
+// Persistent batch scheduler (k_icp_persistent): the registrations of a
+// batch call advance independently through one launch.  A job is one
+// Gauss-Newton iteration of one registration: its
+// tiles are published under consecutive ticket numbers; workers take tickets
+// in order, process the tile, and the last tile of a job to finish reduces
+// the job's partials, updates the registration and publishes its next job.
+struct SchedJob {
+    int level, mode, iter, ntiles;  // pyramid level, MODE_ITER (MODE_EVAL: done), iteration within the level, tiles
+};
+
+struct Sched {
+    unsigned int next_ticket;  // tickets handed out
+    unsigned int published;    // tickets that carry a tile
+    int outstanding;           // registrations whose iterations have not finished
+    int error;                 // 1: a worker stopped waiting (spin limit): the call's results are incomplete
+    unsigned int epoch;        // call number; tile-map entries of this call carry it
+    int pad[3];
+};
+
+struct SchedArgs {
+    Sched *sched;
+    unsigned long long *tile_map;  // [map_size]: (epoch << 32) | (registration << 10) | tile
+    SchedJob *jobs;                // [n]: the job in flight of each registration
+    int *arrived;                  // [n]: its tiles finished so far
+    const Inst *insts;             // [n]
+    ups_icp_result *results;       // [n]
+    const uint8_t *mask;           // [n] or null: registrations taking part (k_sched_init)
+    int n, map_size, levels;
+    int kpt[4];                    // pixels per thread of a tile at each level (<= the kernel's K)
+    int iters[4];
+    float d_max2[4];
+    float cos_theta, irls_delta;
+    int min_inliers;
+    double stop_norm;
 };
 
 // Loop-closure grid search over candidate transforms (see ups_grid.hip).
@@ -92,6 +140,14 @@ ups_status launch_icp_batch_list_irls(int K, int prec, int mode, const Inst *ins
                                       const int *list, const int *start_l, int n, const StepArgs &a, int blocks,
                                       hipStream_t s);
 ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s);
+// Scheduler set-up (first jobs of the registrations taking part) and the
+// persistent launch (grid = resident blocks of the kernel).
+ups_status launch_sched_init(const SchedArgs &A, hipStream_t s);
+ups_status launch_icp_persistent(int K, int prec, const SchedArgs &A, int blocks, hipStream_t s);
+// Resident blocks of the persistent kernel for (K, prec, IRLS) on the current device.
+int persistent_grid(int K, int prec, bool irls);
+// pixels per thread the persistent kernel is instantiated for
+bool persistent_k_supported(int K);
 ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
 ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
                                    const StepArgs &a, hipStream_t s);

@@ -6,8 +6,9 @@
 namespace ups {
 
 template <int K, int PREC>
-static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
+static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a0, int blocks,
                            hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_batch<K, PREC, MODE_ITER, false>), dim3(blocks), dim3(kBlock), 0, s, insts,
                            tile_start, n, a);

@@ -13,7 +13,8 @@ static bool irls_precision_ok(int prec) {
 }
 
 template <int K>
-static void launch_one_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
+static void launch_one_t(int mode, const Inst &I, const StepArgs &a0, int blocks, hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     constexpr int P = UPS_PREC_KAHAN_F64;
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_one<K, P, MODE_ITER, false, true>), dim3(blocks), dim3(kBlock), 0, s, I, a);
@@ -30,8 +31,9 @@ ups_status launch_icp_one_irls(int K, int prec, int mode, const Inst &I, const S
 }
 
 template <int K>
-static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a, int blocks,
+static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a0, int blocks,
                            hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     constexpr int P = UPS_PREC_KAHAN_F64;
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_batch<K, P, MODE_ITER, true>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
@@ -51,7 +53,8 @@ ups_status launch_icp_batch_irls(int K, int prec, int mode, const Inst *insts, c
 
 template <int K>
 static void launch_list_t(int mode, const Inst *insts, const Compact *hdr, const int *list, const int *start_l,
-                          const StepArgs &a, int blocks, hipStream_t s) {
+                          const StepArgs &a0, int blocks, hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     constexpr int P = UPS_PREC_KAHAN_F64;
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_batch_list<K, P, MODE_ITER, true>), dim3(blocks), dim3(kBlock), 0, s, insts, hdr,

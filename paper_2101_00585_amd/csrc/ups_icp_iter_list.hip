@@ -6,7 +6,8 @@ namespace ups {
 
 template <int K, int PREC>
 static void launch_list_t(int mode, const Inst *insts, const Compact *hdr, const int *list, const int *start_l,
-                          const StepArgs &a, int blocks, hipStream_t s) {
+                          const StepArgs &a0, int blocks, hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_batch_list<K, PREC, MODE_ITER, false>), dim3(blocks), dim3(kBlock), 0, s, insts,
                            hdr, list, start_l, a);

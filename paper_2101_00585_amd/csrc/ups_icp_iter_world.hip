@@ -5,7 +5,8 @@
 namespace ups {
 
 template <int K, int PREC>
-static void launch_t(int mode, const Inst &I, const StepArgs &a, int blocks, hipStream_t s) {
+static void launch_t(int mode, const Inst &I, const StepArgs &a0, int blocks, hipStream_t s) {
+    const StepArgs a = with_tile_order(a0);
     if (mode == MODE_ITER)
         hipLaunchKernelGGL((k_icp_one<K, PREC, MODE_ITER, true, false>), dim3(blocks), dim3(kBlock), 0, s, I, a);
     else

@@ -168,9 +168,53 @@ __device__ __forceinline__ void add_terms(ThreadAcc<PREC, NV> &acc, const Pair &
 // (value v at part_out[v * pstride + tile]), in a fixed order: quad sums by
 // DPP, the 64 quad sums of each value through LDS, then 8 threads per value
 // (thread g adds quads g, g+8, ..., g+56 pairwise) and oct_sum.
-template <int NV, typename Acc>
+// ------------------------------------- agent-coherent words (batch scheduler)
+//
+// Data that blocks of one launch hand to each other (block partials,
+// registration state, jobs, counters) is read and written only through
+// relaxed agent-scope atomics, which the hardware keeps coherent across the
+// XCDs' L2 caches without writing back or invalidating them.  A writer orders
+// its data before the word that publishes it by waiting for its stores to
+// complete (wait_stores); a reader has the published word in hand before it
+// loads the data.
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double ld_coh_d(const double *p) {
+    return __longlong_as_double((long long)ld_coh((const unsigned long long *)p));
+}
+
+__device__ __forceinline__ void st_coh_d(double *p, double v) {
+    st_coh((unsigned long long *)p, (unsigned long long)__double_as_longlong(v));
+}
+
+constexpr int kStateWords = (int)(sizeof(RegState) / 4);
+
+// A registration state copied word by word by threads 0 .. kStateWords-1.
+__device__ __forceinline__ void state_ld_coh(RegState &dst, const RegState *src) {
+    if (threadIdx.x < kStateWords)
+        ((uint32_t *)&dst)[threadIdx.x] = ld_coh(((const uint32_t *)src) + threadIdx.x);
+}
+
+__device__ __forceinline__ void state_st_coh(RegState *dst, const RegState &src) {
+    if (threadIdx.x < kStateWords)
+        st_coh(((uint32_t *)dst) + threadIdx.x, ((const uint32_t *)&src)[threadIdx.x]);
+}
+
+// WAVE0: the NV totals are staged in LDS (stage[NV]) and stored by the first
+// wavefront as agent-coherent words.
+template <int NV, typename Acc, bool WAVE0 = false>
 __device__ __forceinline__ void block_partial(const Acc (&x)[NV], Acc (*qbuf)[65], double *part_out, int pstride,
-                                              int tile) {
+                                              int tile, Acc *stage = nullptr) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < NV; v++) {
@@ -187,7 +231,13 @@ __device__ __forceinline__ void block_partial(const Acc (&x)[NV], Acc (*qbuf)[65
 #pragma unroll
         for (int k = 0; k < w; k++) y[k] += y[k + w];
     const Acc t = oct_sum<Acc>(y[0]);
-    if (g == 0 && (tid >> 3) < NV) part_out[(size_t)v * pstride + tile] = (double)t;
+    if constexpr (WAVE0) {
+        if (g == 0 && (tid >> 3) < NV) stage[v] = t;
+        __syncthreads();
+        if (tid < NV) st_coh_d(part_out + (size_t)tid * pstride + tile, (double)stage[tid]);
+    } else {
+        if (g == 0 && (tid >> 3) < NV) part_out[(size_t)v * pstride + tile] = (double)t;
+    }
 }
 
 typedef double v2d __attribute__((ext_vector_type(2)));
@@ -199,28 +249,29 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // sixteen pair sums as a tree), chunk by chunk, then oct_sum.  Every thread
 // of the group returns the same total, and every block that reads the same
 // partials computes the same totals.
-template <int NV, typename Acc>
+// NL: 16-byte loads in flight per thread (a chunk of 16 NL partials).
+template <int NV, typename Acc, int NL = 16>
 __device__ __forceinline__ Acc sum_partials(const double *part, int pstride, int n) {
     const int v = min((int)(threadIdx.x >> 3), NV - 1), g = threadIdx.x & 7;
     const UPS_AS_GLOBAL double *pv = (const UPS_AS_GLOBAL double *)part + (size_t)v * pstride;
     Acc t = 0;
-    for (int b0 = 0; b0 < n; b0 += 256) {
-        const int nk = min(16, (n - b0 + 15) >> 4);  // block-uniform
-        v2d x[16];
+    for (int b0 = 0; b0 < n; b0 += 16 * NL) {
+        const int nk = min(NL, (n - b0 + 15) >> 4);  // block-uniform
+        v2d x[NL];
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
+        for (int k = 0; k < NL; k++) {
             // an index past the last partial is clamped into the row and its value unused
             x[k] = (v2d){0.0, 0.0};
             if (k < nk) x[k] = *(const UPS_AS_GLOBAL v2d *)(pv + min(b0 + 16 * k + 2 * g, pstride - 2));
         }
-        Acc y[16];
+        Acc y[NL];
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
+        for (int k = 0; k < NL; k++) {
             const int b = b0 + 16 * k + 2 * g;
             y[k] = ((b < n) ? (Acc)x[k].x : Acc(0)) + ((b + 1 < n) ? (Acc)x[k].y : Acc(0));
         }
 #pragma unroll
-        for (int w = 8; w >= 1; w >>= 1)
+        for (int w = NL / 2; w >= 1; w >>= 1)
 #pragma unroll
             for (int k = 0; k < w; k++) y[k] += y[k + w];
         t += y[0];
@@ -230,9 +281,9 @@ __device__ __forceinline__ Acc sum_partials(const double *part, int pstride, int
 
 // The totals of the first n partials into tot[0 .. NV-1] (LDS), visible to
 // the whole block on return.
-template <int NV, typename Acc>
+template <int NV, typename Acc, int NL = 16>
 __device__ __forceinline__ void reduce_partials(const double *part, int pstride, int n, Acc *tot) {
-    const Acc t = sum_partials<NV, Acc>(part, pstride, n);
+    const Acc t = sum_partials<NV, Acc, NL>(part, pstride, n);
     if ((threadIdx.x & 7) == 0 && (threadIdx.x >> 3) < NV) tot[threadIdx.x >> 3] = t;
     __syncthreads();
 }
@@ -368,6 +419,174 @@ __device__ void gn_step(const StepArgs &a, const T *tot, RegState &S) {
     if (a.stop_norm > 0.0 && S.last_norm < a.stop_norm) S.level_active = 0;
 }
 
+// -------------------------------------------- wavefront-parallel FP64 solve
+
+// v as held by lane `lane` (the same lane in every lane of the wavefront).
+template <typename T>
+__device__ __forceinline__ T lane_bcast(T v, int lane) {
+    if constexpr (sizeof(T) == 8) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+    }
+}
+
+// v as held by lane src (a lane of its own for every lane, 0 <= src < 64).
+template <typename T>
+__device__ __forceinline__ T lane_fetch(T v, int src) {
+    if constexpr (sizeof(T) == 8) {
+        const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+        const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+        return __hiloint2double(hi, lo);
+    } else {
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+    }
+}
+
+// Index of entry (i, j), i <= j, in the row-major upper triangle of a 6x6 matrix.
+__device__ __forceinline__ int tri6(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
+
+// Gauss-Newton step from the reduced totals (J^T J upper triangle in tot[0..20],
+// J^T r in tot[21..26], inlier count in tot[28]), computed by one whole
+// wavefront: every lane of it calls this with the same arguments.  The same
+// update as gn_step with a few registers per lane instead of the whole 6x6
+// factor in one thread's (the persistent batch kernel, whose occupancy the
+// solve's registers would otherwise set); slower on its own than gn_step,
+// whose chain of FP64 operations has no cross-lane waits.  Lane 6r+c
+// holds entry (r, c) of the 6x6 matrix.  Cholesky column by column (pivot
+// broadcast from its lane, column scaled by the pivot's inverse square root,
+// trailing entries updated with the column's values fetched from their lanes:
+// the same operations in the same order as the textbook column loop), then
+// forward and back substitution for xi = -A^-1 b with the right-hand side in
+// lanes 0..5, then T <- Exp(xi) T with one output entry per lane (R in lanes
+// 0..8, t in lanes 9..11).  A pivot <= 1e-12 x the largest diagonal entry,
+// or fewer than min_inliers inliers, stops the registration with the pose
+// unchanged.  Lane 0 updates the iteration counts, the step norm and the
+// level's convergence.  S is the block's state copy (LDS).
+template <typename T>
+__device__ void gn_step_wave(const StepArgs &a, const T *tot, RegState &S) {
+    const int lane = threadIdx.x & 63;
+    if ((double)tot[28] < (double)a.min_inliers) {
+        if (lane == 0) {
+            S.status = UPS_NO_INLIERS;
+            S.stop = 1;
+        }
+        return;
+    }
+    const int r = lane / 6, c = lane - 6 * (lane / 6);
+    const bool mat = lane < 36;
+    T x = mat ? tot[r <= c ? tri6(r, c) : tri6(c, r)] : T(0);
+    T maxd = 0;
+#pragma unroll
+    for (int d = 0; d < 6; d++) {
+        const T v = tot[tri6(d, d)];
+        maxd = v > maxd ? v : maxd;
+    }
+    bool ok = maxd > T(0);
+    T inv[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const T d = lane_bcast(x, 7 * j);
+        ok = ok && d > T(1e-12) * maxd;
+        inv[j] = ok ? inv_sqrt<T>(d) : T(0);
+        if (c == j && r >= j) x *= inv[j];  // column j of L (the pivot becomes sqrt(d))
+        const T lr = lane_fetch(x, min(6 * r + j, 63)), lc = lane_fetch(x, min(6 * c + j, 63));
+        if (mat && r > j && c > j) x -= lr * lc;
+    }
+    if (!ok) {
+        if (lane == 0) {
+            S.status = UPS_DEGENERATE;
+            S.stop = 1;
+        }
+        return;
+    }
+    // forward substitution L y = -b (lane i < 6 holds row i), then L^T xi = y
+    T z = lane < 6 ? -tot[21 + lane] : T(0);
+    {
+        T Lrow[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) Lrow[j] = lane_fetch(x, min(6 * lane + j, 63));  // L[lane][j]
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            if (lane == j) z *= inv[j];
+            const T yj = lane_bcast(z, j);
+            if (lane > j && lane < 6) z -= Lrow[j] * yj;
+        }
+    }
+    T Lcol[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) Lcol[j] = lane_fetch(x, min(6 * j + lane, 63));  // L[j][lane]
+    T xi[6];
+#pragma unroll
+    for (int j = 5; j >= 0; j--) {
+        if (lane == j) z *= inv[j];
+        xi[j] = lane_bcast(z, j);
+        if (lane < j) z -= Lcol[j] * xi[j];
+    }
+    // T <- Exp(xi) T: Rodrigues rotation E and the V matrix; below |omega| =
+    // 1/4 the coefficients sin(th)/th, (1-cos th)/th^2 and (th-sin th)/th^3
+    // from their Taylor series to the th^10 term (the first omitted term,
+    // th^12/13! for the first, is below 1e-17), else the closed forms
+    const T w0 = xi[0], w1 = xi[1], w2 = xi[2];
+    const T th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    T A, B, C;
+    if (th2 < T(0.0625)) {
+        // 1/n! for n = 0..13
+        constexpr double f[14] = {1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040,
+                                  1.0 / 40320, 1.0 / 362880, 1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600,
+                                  1.0 / 6227020800.0};
+        A = B = C = 0;
+#pragma unroll
+        for (int k = 5; k >= 0; k--) {
+            const T sg = (k & 1) ? T(-1) : T(1);
+            A = A * th2 + sg * (T)f[2 * k + 1];
+            B = B * th2 + sg * (T)f[2 * k + 2];
+            C = C * th2 + sg * (T)f[2 * k + 3];
+        }
+    } else {
+        const T th = sqrt(th2);
+        A = sin(th) / th;
+        B = (T(1) - cos(th)) / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    const T K[3][3] = {{0, -w2, w1}, {w2, 0, -w0}, {-w1, w0, 0}};
+    const int row = lane < 9 ? lane / 3 : (lane < 12 ? lane - 9 : 0);
+    T E[3], V[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+        T K2 = 0;
+#pragma unroll
+        for (int q = 0; q < 3; q++) K2 += (row == 0 ? K[0][q] : row == 1 ? K[1][q] : K[2][q]) * K[q][m];
+        const T Krm = row == 0 ? K[0][m] : row == 1 ? K[1][m] : K[2][m];
+        const T I = (row == m) ? T(1) : T(0);
+        E[m] = I + A * Krm + B * K2;
+        V[m] = I + B * Krm + C * K2;
+    }
+    T out = 0;
+    if (lane < 9) {
+        const int col = lane - 3 * row;
+        out = E[0] * (T)S.R[col] + E[1] * (T)S.R[3 + col] + E[2] * (T)S.R[6 + col];
+    } else if (lane < 12) {
+        const T te = V[0] * xi[3] + V[1] * xi[4] + V[2] * xi[5];
+        out = E[0] * (T)S.t[0] + E[1] * (T)S.t[1] + E[2] * (T)S.t[2] + te;
+    }
+    // every lane has read the old pose before any lane writes the new one
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 9) S.R[lane] = (double)out;
+    else if (lane < 12) S.t[lane - 9] = (double)out;
+    if (lane == 0) {
+        S.iters_run += 1;
+        S.level_iters[a.prev_level] += 1;
+        T nrm = 0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) nrm += xi[k] * xi[k];
+        S.last_norm = (double)sqrt(nrm);
+        if (a.stop_norm > 0.0 && S.last_norm < a.stop_norm) S.level_active = 0;
+    }
+}
+
 // ------------------------------------------------------------------ kernel
 
 // Partials a launch over `nblocks` blocks leaves for its successor: one per
@@ -381,9 +600,19 @@ __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nbloc
 // WORLD: the world-frame variant (state pose = the scan's world pose).
 // IRLS: the absolute-value objective of Equation 1, each inlier's terms
 // weighted by 1 / max(|r|, a.irls_delta).
+// LDS workspace of one block's tile (one per kernel, whichever modes it runs).
+template <typename Acc>
+struct IcpShared {
+    RegState S;
+    Acc qbuf[31][65];
+    Acc tot[32];
+    int active;
+    int job[8];  // persistent scheduler: ticket's registration and tile, last-arriver flag, spare, job (4 words)
+};
+
 template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS>
-__device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
-    constexpr int NV = (MODE == MODE_ITER) ? 29 : 31;  // EVAL adds valid count and truncated cost
+__device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int tile, IcpShared<AccOf<PREC>> &sh) {
+    constexpr int NV = (MODE == MODE_EVAL) ? 31 : 29;  // EVAL adds valid count and truncated cost
     using Acc = AccOf<PREC>;
     const int tid = threadIdx.x;
     const int l = a.level;
@@ -392,15 +621,17 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     const double *part_in = I.partials + (size_t)a.parity * I.pstride * kPartialStride;
     double *part_out = I.partials + (size_t)(FUSED ? (a.parity ^ 1) : 0) * I.pstride * kPartialStride;
 
-    __shared__ RegState S;
-    __shared__ Acc qbuf[31][65];
-    __shared__ Acc tot[32];
-    __shared__ int active;
+    RegState &S = sh.S;
+    Acc(&qbuf)[31][65] = sh.qbuf;
+    Acc(&tot)[32] = sh.tot;
+    int &active = sh.active;
     const DGeom sg = I.sg[l], kg = I.kg[l];
     const float4 *__restrict__ scan = I.scan[l];
     const float4 *__restrict__ kf = I.kf[l];
     const int npix = sg.rows * sg.cols;
-    const int base = tile * (kBlock * K);
+    // pixels per thread of this tile: K, or fewer for a scheduled tile
+    const int KL = (MODE == MODE_SCHED) ? a.kpt : K;
+    const int base = tile * (kBlock * KL);
 
     // ---- issue the independent loads together: the first pair of scan
     // surfels and their ray-table columns, the previous launch's block
@@ -426,11 +657,11 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     if (!FUSED) {
         if (MODE == MODE_ITER && !slot_in->active) return;  // uniform: the whole block leaves
         if (MODE == MODE_EVAL && slot_in->skip) return;
-        if (tid == 0) S = *slot_in;
+        if constexpr (MODE == MODE_SCHED) state_ld_coh(S, slot_in);
+        else if (tid == 0) S = *slot_in;
         __syncthreads();
     } else {
         // the state, one 32-bit word per thread, loaded alongside the partials
-        constexpr int kStateWords = (int)(sizeof(RegState) / 4);
         static_assert(sizeof(RegState) % 4 == 0 && kStateWords <= kBlock, "state copy");
         uint32_t sword = 0;
         if (tid < kStateWords) sword = ((const UPS_AS_GLOBAL uint32_t *)slot_in)[tid];
@@ -476,7 +707,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     constexpr int GP = K < 4 ? K : 4;
     bool done = false;
 #pragma unroll 2
-    for (int k0 = 0; k0 < K; k0 += GP) {
+    for (int k0 = 0; k0 < KL; k0 += GP) {
 #pragma unroll
         for (int k = k0; k < k0 + GP; k += P) {
             if (pw >= npix) {
@@ -498,7 +729,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
                 __builtin_amdgcn_sched_barrier(0);
             }
             {
-                const bool more = k + P < K;
+                const bool more = k + P < KL;
 #pragma unroll
                 for (int u = 0; u < P; u++) {
                     jc[u] += more ? P * col_step : 0;
@@ -544,7 +775,7 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
         Acc x[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
-        block_partial<NV, Acc>(x, qbuf, part_out, I.pstride, tile);
+        block_partial<NV, Acc, MODE == MODE_SCHED>(x, qbuf, part_out, I.pstride, tile, tot);
     }
     if (FUSED && tile == 0 && tid == 0) {
         S.pending = (MODE == MODE_ITER);
@@ -553,19 +784,27 @@ __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int 
     }
 }
 
+template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS>
+__device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
+    __shared__ IcpShared<AccOf<PREC>> sh;
+    icp_tile<K, PREC, MODE, FUSED, WORLD, IRLS>(I, a, tile, sh);
+}
+
 // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and
 // each XCD has its own L2: the tiles are permuted so that the workgroups of
 // one XCD take a contiguous run of tiles, and neighbouring tiles of a
 // registration, whose keyframe gathers share cache lines, meet in one L2.
-// Any other dealing still covers every tile once.
-__device__ __forceinline__ int xcd_tile(int blk, int nblk) {
+// Any other dealing still covers every tile once; the debug order reverses
+// it (the partials are reduced in tile order, so results do not change).
+__device__ __forceinline__ int xcd_tile(int blk, int nblk, int reverse) {
     const int x = blk & 7, q = blk >> 3, per = nblk >> 3, rem = nblk & 7;
-    return x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+    const int t = x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+    return reverse ? nblk - 1 - t : t;
 }
 
 template <int K, int PREC, int MODE, bool WORLD, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
-    icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, xcd_tile(blockIdx.x, gridDim.x));
+    icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles));
 }
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix
@@ -573,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 template <int K, int PREC, int MODE, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
                                                       const int *__restrict__ tile_start, int n, StepArgs a) {
-    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int b = xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles);
     int lo = 0, hi = n;  // the last k with tile_start[k] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
@@ -591,7 +830,8 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restric
                                                            const int *__restrict__ list,
                                                            const int *__restrict__ start, StepArgs a) {
     const int cnt = hdr->count, total = hdr->total[a.level];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    for (int t0 = blockIdx.x; t0 < total; t0 += gridDim.x) {
+        const int t = a.reverse_tiles ? total - 1 - t0 : t0;
         int lo = 0, hi = cnt;  // the last m with start[m] <= t
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -645,6 +885,10 @@ __global__ __launch_bounds__(kBlock) void k_solve_batch_list(const Inst *__restr
 // One block: the evaluation partials -> result (quality at the final pose,
 // plus the state's pose, status, iteration count and last step norm), or ->
 // normal equations.
+template <typename Acc>
+__device__ void write_result(const Inst &I, const RegState *S, const Acc *tot, ups_icp_result *res,
+                             ups_normal_eq *neq);
+
 template <int PREC>
 __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_result *res, ups_normal_eq *neq) {
     using Acc = AccOf<PREC>;
@@ -654,6 +898,15 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_
     reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, I.pstride,
                              npartials_of(I.nblocks[0]), tot);
     if (threadIdx.x != 0) return;
+    write_result<Acc>(I, S, tot, res, neq);
+}
+
+// The result of a registration (quality at the final pose from the 31
+// evaluation totals, plus the state's pose, status, iteration counts and last
+// step norm), or its normal equations.
+template <typename Acc>
+__device__ void write_result(const Inst &I, const RegState *S, const Acc *tot, ups_icp_result *res,
+                             ups_normal_eq *neq) {
     const double n_in = (double)tot[28], n_valid = (double)tot[29];
     if (res) {
         ups_icp_result *r = res;
@@ -718,6 +971,257 @@ __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
     if (threadIdx.x == 0) S->npartials = 1;
 }
 
+
+// Value v = tid / 8 (clamped to NV - 1) summed over the first n block
+// partials through agent-coherent loads: thread g of the group adds partials
+// g, g + 8, ... in order, then oct_sum; the totals into tot (LDS), visible
+// to the whole block on return.  The same sums whatever the blocks' order of
+// arrival.
+template <int NV, typename Acc>
+__device__ __forceinline__ void reduce_partials_coh(const double *part, int pstride, int n, Acc *tot) {
+    const int v = min((int)(threadIdx.x >> 3), NV - 1), g = threadIdx.x & 7;
+    const double *pv = part + (size_t)v * pstride;
+    Acc t = 0;
+    for (int b0 = 0; b0 < n; b0 += 64) {
+        // eight loads in flight per thread; an index past the last partial is
+        // clamped and its value unused
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) x[q] = ld_coh_d(pv + min(b0 + g + 8 * q, n - 1));
+#pragma unroll
+        for (int q = 0; q < 8; q++) t += (b0 + g + 8 * q < n) ? (Acc)x[q] : Acc(0);
+    }
+    t = oct_sum<Acc>(t);
+    if ((threadIdx.x & 7) == 0 && (threadIdx.x >> 3) < NV) tot[threadIdx.x >> 3] = t;
+    __syncthreads();
+}
+
+// ------------------------------------------------- persistent batch scheduler
+//
+// One launch runs every registration of a batch call through its
+// Gauss-Newton iterations.  Each registration has one job in flight (an
+// iteration at a level); a job's tiles carry consecutive ticket numbers,
+// recorded in the tile map with the call's epoch and the job's level.  A
+// worker block takes the next ticket, waits until its tile is published,
+// processes it (the iteration kernel's tile body), writes its block partial
+// and counts itself in the registration's arrivals.  The block that completes
+// a job reduces the job's partials in tile order (the same sums whatever the
+// order of arrival), applies the update in FP64 and publishes the next job,
+// or, after the last iteration, counts the registration out.  Registrations
+// that converge stop publishing, so the launch's work follows the active
+// registrations.  A worker leaves when every registration is done, or, as a
+// last resort against a broken protocol, after kSpinLimit polls (error flag).
+// Everything blocks hand to each other goes through agent-coherent words
+// (ld_coh / st_coh), published after wait_stores.  The evaluation at the final
+// poses is the launch that follows.
+
+// polls of a waiting worker before it gives up (each after a short sleep;
+// seconds in all, while normal waits are microseconds)
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ int sched_ntiles(const SchedArgs &A, const Inst &I, int level) {
+    const int np = I.sg[level].rows * I.sg[level].cols, K = A.kpt[level];
+    return (np + kBlock * K - 1) / (kBlock * K);
+}
+
+// The first job: the coarsest level with iterations, else the evaluation.
+__device__ __forceinline__ SchedJob first_job(const SchedArgs &A, const Inst &I) {
+    int l = A.levels - 1;
+    while (l >= 0 && A.iters[l] == 0) l--;
+    SchedJob J;
+    J.level = l >= 0 ? l : 0;
+    J.mode = l >= 0 ? MODE_ITER : MODE_EVAL;
+    J.iter = 0;
+    J.ntiles = sched_ntiles(A, I, J.level);
+    return J;
+}
+
+// The job after J, given the state S after J's update: the next iteration of
+// the level while it has not converged, else the first iteration of the next
+// finer level with iterations, else the evaluation.  As in the launch
+// sequence: a level that converged or a registration that stopped skips its
+// remaining iterations; MAX_ITERS when a stop criterion is set and level 0
+// ends without meeting it.
+__device__ __forceinline__ SchedJob next_job(const SchedArgs &A, const Inst &I, const SchedJob &J, RegState &S) {
+    SchedJob N;
+    N.iter = 0;
+    if (!S.stop && S.level_active && J.iter + 1 < A.iters[J.level]) {
+        N.level = J.level;
+        N.mode = MODE_ITER;
+        N.iter = J.iter + 1;
+    } else {
+        int l = J.level - 1;
+        while (l >= 0 && A.iters[l] == 0) l--;
+        if (!S.stop && l >= 0) {
+            S.level_active = 1;
+            N.level = l;
+            N.mode = MODE_ITER;
+        } else {
+            if (J.level == 0 && A.stop_norm > 0.0 && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
+            N.level = 0;
+            N.mode = MODE_EVAL;
+        }
+    }
+    N.ntiles = sched_ntiles(A, I, N.level);
+    S.active = N.mode == MODE_ITER;
+    return N;
+}
+
+// Tile-map word of a job's tiles (the tile index goes in bits 0..9):
+// epoch << 32 | mode << 31 | level << 29 | registration << 10.
+__device__ __forceinline__ unsigned long long sched_tag(unsigned epoch, int k, const SchedJob &J) {
+    return ((unsigned long long)epoch << 32) | ((unsigned long long)(unsigned)J.mode << 31) |
+           ((unsigned long long)(unsigned)J.level << 29) | ((unsigned long long)(unsigned)k << 10);
+}
+
+// The block that finished job J of registration k: reduce the job's partials,
+// then either update the registration and publish its next job, or write its
+// result and count it out.  Not inlined: it runs once per job, and inlined
+// into the tile loop its registers would lower the worker's occupancy.
+template <int PREC>
+__device__ __noinline__ void sched_complete(const SchedArgs &A, const Inst &I, int k, const SchedJob &J,
+                                            unsigned epoch, IcpShared<AccOf<PREC>> &sh) {
+    using Acc = AccOf<PREC>;
+    RegState &S = sh.S;  // the tile's copy is free again
+    reduce_partials_coh<29, Acc>(I.partials, I.pstride, J.ntiles, sh.tot);
+    state_ld_coh(S, I.state);
+    if (threadIdx.x == 0) sh.job[6] = ld_coh(&A.jobs[k].iter);  // the iteration within the level
+    __syncthreads();
+    {
+        if (threadIdx.x < 64 && !S.stop) {
+            StepArgs a;
+            memset(&a, 0, sizeof(a));
+            a.prev_level = J.level;
+            a.min_inliers = A.min_inliers;
+            a.stop_norm = A.stop_norm;
+            gn_step_wave<Acc>(a, sh.tot, S);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            SchedJob Jc = J;
+            Jc.iter = sh.job[6];
+            const SchedJob N = next_job(A, I, Jc, S);
+            sh.job[4] = N.level;
+            sh.job[5] = N.mode;
+            sh.job[6] = N.iter;
+            sh.job[7] = N.ntiles;
+        }
+        __syncthreads();
+        // the new state, job and arrival count, then their tiles; after the
+        // last iteration the registration is done (the evaluation launch
+        // that follows this kernel takes its final state)
+        state_st_coh(I.state, S);
+        const bool done = sh.job[5] == MODE_EVAL;
+        unsigned base = 0;
+        if (threadIdx.x == 0) {
+            int *jw = (int *)(A.jobs + k);
+            for (int q = 0; q < 4; q++) st_coh(jw + q, sh.job[4 + q]);
+            st_coh(A.arrived + k, 0);
+            // the new job's tickets, reserved while the stores complete
+            if (!done)
+                base = __hip_atomic_fetch_add(&A.sched->published, (unsigned)sh.job[7], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x < 64) wait_stores();  // the first wavefront wrote all of them
+        if (threadIdx.x == 0 && done) {
+            __hip_atomic_fetch_add(&A.sched->outstanding, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (threadIdx.x == 0) {
+            const int nt = sh.job[7];
+            if (base + (unsigned)nt > (unsigned)A.map_size) st_coh(&A.sched->error, 1);
+            SchedJob N;
+            N.level = sh.job[4];
+            N.mode = sh.job[5];
+            const unsigned long long tag = sched_tag(epoch, k, N);
+            for (int i = 0; i < nt; i++)
+                if (base + i < (unsigned)A.map_size) st_coh(A.tile_map + base + i, tag | (unsigned)i);
+        }
+    }
+}
+
+// The persistent worker (grid = the blocks that fit on the device at once).
+// Thread 0 holds the ticket the block works on next: it takes it when it
+// starts a tile and polls it after the tile (the first poll issued beside the
+// tile's arrival), so the ticket's round trips overlap the tile's work.
+template <int K, int PREC, bool IRLS>
+__global__ __launch_bounds__(kBlock) void k_icp_persistent(SchedArgs A, const Inst *__restrict__ insts) {
+    using Acc = AccOf<PREC>;
+    __shared__ IcpShared<Acc> sh;
+    const unsigned epoch = A.sched->epoch;
+    unsigned t_next = 0;          // thread 0: the next ticket
+    unsigned long long v_first = 0;  // thread 0: its first poll, issued with the arrival
+    if (threadIdx.x == 0) t_next = __hip_atomic_fetch_add(&A.sched->next_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int k = -1, tile = 0, level = 0, mode = 0;
+            const unsigned t = t_next;
+            if (t < (unsigned)A.map_size) {
+                // relaxed polls: no cache maintenance while waiting
+                for (unsigned spin = 0;; spin++) {
+                    const unsigned long long v = spin == 0 && v_first != 0 ? v_first : ld_coh(A.tile_map + t);
+                    if ((unsigned)(v >> 32) == epoch) {
+                        k = (int)((v >> 10) & 0xFFFFu);
+                        tile = (int)(v & 1023u);
+                        level = (int)((v >> 29) & 3u);
+                        mode = (int)((v >> 31) & 1u);
+                        break;
+                    }
+                    if ((spin & 15u) == 15u && ld_coh(&A.sched->outstanding) <= 0) {
+                        // every registration is done: no tile will be published under this ticket
+                        break;
+                    }
+                    if (spin >= kSpinLimit) {
+                        st_coh(&A.sched->error, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+            if (k >= 0)
+                t_next = __hip_atomic_fetch_add(&A.sched->next_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sh.job[0] = k;
+            sh.job[1] = tile;
+            sh.job[4] = level;
+            sh.job[5] = mode;
+        }
+        __syncthreads();
+        // wave-uniform: the registration's descriptor then comes through scalar loads
+        const int k = __builtin_amdgcn_readfirstlane(sh.job[0]), tile = __builtin_amdgcn_readfirstlane(sh.job[1]);
+        if (k < 0) return;  // block-uniform
+        const Inst &I = insts[k];
+        SchedJob J;
+        J.level = __builtin_amdgcn_readfirstlane(sh.job[4]);
+        J.mode = __builtin_amdgcn_readfirstlane(sh.job[5]);
+        J.iter = 0;  // read from the job record by the block that completes the job
+        J.ntiles = sched_ntiles(A, I, J.level);
+        StepArgs a;
+        memset(&a, 0, sizeof(a));
+        a.level = J.level;
+        a.prev_level = -1;
+        a.d_max2 = A.d_max2[J.level];
+        a.tau2 = A.d_max2[0];
+        a.cos_theta = A.cos_theta;
+        a.irls_delta = A.irls_delta;
+        a.min_inliers = A.min_inliers;
+        a.stop_norm = A.stop_norm;
+        a.kpt = A.kpt[J.level];
+        icp_tile<K, PREC, MODE_SCHED, false, false, IRLS>(I, a, tile, sh);
+        // the tile's partial (stored by the first wavefront) before its arrival
+        if (threadIdx.x < 64) {
+            wait_stores();
+            if (threadIdx.x == 0) {
+                const int old = __hip_atomic_fetch_add(A.arrived + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v_first = t_next < (unsigned)A.map_size ? ld_coh(A.tile_map + t_next) : 0ull;
+                sh.job[2] = old == J.ntiles - 1;
+            }
+        }
+        __syncthreads();
+        if (sh.job[2]) {
+            sched_complete<PREC>(A, I, k, J, epoch, sh);
+            if (threadIdx.x == 0) v_first = 0;  // the block published tiles: poll afresh
+        }
+        __syncthreads();
+    }
+}
 
 // Compile-time dispatch of (pixels per thread, precision, mode).
 #define UPS_CASE_K(KV, ...)         \

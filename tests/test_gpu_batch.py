@@ -20,6 +20,21 @@ pytestmark = pytest.mark.gpu
 BATCH_PARAMS = dict(levels=3, iters=(10, 10, 10), stop_update_norm=1e-6)
 
 
+def assert_status_matches(res, ref, stop_norm):
+    """Equal statuses, except where the stop criterion decided them at its
+    threshold: a level that needs its last allowed iteration to bring the
+    update norm below stop_norm converges on one side (CONVERGED) and runs out
+    of iterations on the other (MAX_ITERS), FP32 against FP64 sums; then the
+    side that did not converge ended with an update norm within 10 x the
+    threshold."""
+    if res["status"] == ref["status"]:
+        return
+    pair = {res["status"], ref["status"]}
+    assert pair == {0, 1}, (res["status"], ref["status"])
+    unconverged = res if res["status"] == 1 else ref
+    assert unconverged["last_update_norm"] < 10 * stop_norm, unconverged["last_update_norm"]
+
+
 def _t(x):
     import torch
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
@@ -84,7 +99,8 @@ def test_batch_normals_scans_only(gpu_lib, bctx, pairs):
     b.close()
 
 
-def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs):
+@pytest.mark.parametrize("persistent", [False, True], ids=["launches", "persistent"])
+def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs, persistent):
     import torch
     items, surf = [], []
     for p in pairs:
@@ -94,6 +110,7 @@ def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs):
         surf.append((kf, scan))
         items.append(dict(scan_geom=g, kf_geom=g, scan_surfel=_t(scan), kf_surfel=_t(kf)))
     b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.set_scheduler(persistent)
     res = gpu_lib.read_results(b.register([np.eye(4)] * len(items)))
     for k, (p, (kf, scan)) in enumerate(zip(pairs, surf)):
         g = p["geom"]
@@ -102,7 +119,7 @@ def test_batch_matches_oracle_per_registration(gpu_lib, bctx, pairs):
         print(f"pair {k} {g.rows}x{g.cols} {p['kind']}: GPU vs oracle {rot:.2e} rad {tr:.2e} m, "
               f"iters {res[k]['iters_run']} / {ref['iters_run']}, status {res[k]['status']} / {ref['status']}")
         assert rot < 1e-5 and tr < 1e-5, (k, rot, tr)
-        assert res[k]["status"] == ref["status"]
+        assert_status_matches(res[k], ref, BATCH_PARAMS["stop_update_norm"])
         assert abs(res[k]["iters_run"] - ref["iters_run"]) <= 2
         assert sum(res[k]["level_iters"]) == res[k]["iters_run"]
         assert abs(res[k]["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
@@ -134,12 +151,14 @@ def test_batch_equals_single_registration(gpu_lib, bctx, pairs):
     b.close()
 
 
-def test_batch_graph_replays_match_eager(gpu_lib, bctx, pairs):
+@pytest.mark.parametrize("persistent", [False, True], ids=["launches", "persistent"])
+def test_batch_graph_replays_match_eager(gpu_lib, bctx, pairs, persistent):
     """The whole batched call captured in a HIP graph: each of several
     replays, with eager work in between, reproduces the eager result bitwise."""
     import torch
     items = _items_from_depth(gpu_lib, pairs[:4])
     b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.set_scheduler(persistent)
     init = torch.stack([gpu_lib.pose_tensor(np.eye(4)) for _ in items])
     results = torch.zeros((len(items), gpu_lib.RESULT_BYTES), dtype=torch.uint8, device="cuda")
     b.normals()
@@ -166,7 +185,8 @@ def test_batch_graph_replays_match_eager(gpu_lib, bctx, pairs):
     b.close()
 
 
-def test_batch_failures_isolated(gpu_lib, bctx, pairs):
+@pytest.mark.parametrize("persistent", [False, True], ids=["launches", "persistent"])
+def test_batch_failures_isolated(gpu_lib, bctx, pairs, persistent):
     """An empty registration (no returns) stops with NO_INLIERS without
     disturbing its neighbours in the batch."""
     import torch
@@ -174,6 +194,7 @@ def test_batch_failures_isolated(gpu_lib, bctx, pairs):
     g = items[1]["scan_geom"]
     items[1]["scan_depth"] = torch.zeros((g.rows, g.cols), dtype=torch.float32, device="cuda")
     b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.set_scheduler(persistent)
     b.normals()
     res = gpu_lib.read_results(b.register([np.eye(4)] * 3))
     assert res[1]["status"] == 3 and res[1]["iters_run"] == 0
@@ -185,7 +206,8 @@ def test_batch_failures_isolated(gpu_lib, bctx, pairs):
     b.close()
 
 
-def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs):
+@pytest.mark.parametrize("persistent", [False, True], ids=["launches", "persistent"])
+def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs, persistent):
     """Registrations started 60 deg away end with a low inlier ratio and are
     rerun from the identity; the fallback's result replaces theirs (status
     FALLBACK_USED) and matches a plain identity-started registration, while
@@ -193,6 +215,7 @@ def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs):
     import torch
     items = _items_from_depth(gpu_lib, pairs[:4])
     b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
+    b.set_scheduler(persistent)
     b.normals()
     plain = _np(b.register([np.eye(4)] * 4)).copy()
     bad = synth.se3(synth.rot_z(np.radians(60.0)), [1.5, -1.0, 0.0])
@@ -272,7 +295,7 @@ def test_benchmark_batch_sampled_against_oracle(gpu_lib, bctx):
               f"iters {res[k]['iters_run']} / {ref['iters_run']}, status {res[k]['status']} / {ref['status']}",
               flush=True)
         assert rot < 1e-5 and tr < 1e-5, (k, rot, tr)
-        assert res[k]["status"] == ref["status"]
+        assert_status_matches(res[k], ref, BATCH_PARAMS["stop_update_norm"])
         assert 1 <= res[k]["iters_run"] <= 30 and sum(res[k]["level_iters"]) == res[k]["iters_run"]
         assert abs(res[k]["inliers"] - ref["inliers"]) <= 2e-3 * ref["valid"]
         # the quality block (inlier ratio, rms, truncated cost) at the two final poses
