@@ -194,8 +194,15 @@ def run_single(args, torch, ups, synth, W, stream):
     ctx = ups.Context(0, max_pixels=npix)
 
     # keyframe: GPU normals + GPU fusion of the 10 keyframe scans (setup)
-    kf_base = torch.zeros((g.rows, g.cols, 4), dtype=torch.float32, device=dev)
-    cnt_base = torch.zeros((g.rows, g.cols), dtype=torch.int16, device=dev)
+    # keyframe surfels and sample counts share one allocation (the base copy,
+    # and the working copy restored from it with one device copy per step)
+    kfb = g.rows * g.cols * 16
+
+    def kf_pair():
+        buf = torch.zeros(kfb + g.rows * g.cols * 2, dtype=torch.uint8, device=dev)
+        return buf, buf[:kfb].view(torch.float32).view(g.rows, g.cols, 4), buf[kfb:].view(torch.int16).view(g.rows, g.cols)
+
+    base_buf, kf_base, cnt_base = kf_pair()
     tmp = torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev)
     for d, T in zip(c1["kf_scans"], c1["T_kf_scans"]):
         ups.panorama_normals(ctx, g, torch.from_numpy(d).to(dev), tmp)
@@ -204,8 +211,8 @@ def run_single(args, torch, ups, synth, W, stream):
 
     scan_depth = torch.from_numpy(c1["scan"]).to(dev)
     scan_surf = torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev)
-    kf_work = kf_base.clone()
-    cnt_work = cnt_base.clone()
+    work_buf, kf_work, cnt_work = kf_pair()
+    work_buf.copy_(base_buf)
     init_d = ups.pose_tensor(c1["T_init"], dev)
     result = ups.new_result(dev)
     params = ups.IcpParams(levels=LEVELS, iters=ITERS, precision=PREC[args.precision])
@@ -215,8 +222,7 @@ def run_single(args, torch, ups, synth, W, stream):
     def step():
         ups.panorama_normals(ctx, g, scan_depth, scan_surf)
         ups.register_scan(ctx, g, scan_surf, g, kf_base, init_d, params, result)
-        kf_work.copy_(kf_base)
-        cnt_work.copy_(cnt_base)
+        work_buf.copy_(base_buf)
         ups.fuse_scan(ctx, g, scan_surf, g, kf_work, cnt_work, ups.result_pose(result))
 
     for _ in range(max(1, args.warmup)):

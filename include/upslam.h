@@ -162,8 +162,8 @@ typedef struct ups_context ups_context;
 /* Create a context on `device` for panoramas of up to max_pixels pixels and
  * batches of up to max_batch registrations whose panoramas total at most
  * max_batch_pixels pixels (scan and keyframe each).  The scratch of single
- * registrations, normals and fusion (pyramids, a-trous buffer, fill keys,
- * block partials, state, ray tables) is allocated here; a batch allocates its
+ * registrations, normals and fusion (a-trous buffer, fill keys, block
+ * partials, state, ray tables) is allocated here; a batch allocates its
  * own in ups_batch_create.  The first use of a new panorama geometry
  * uploads its ray tables synchronously; such a first use is rejected during
  * stream capture (UPS_ERR_INVALID_ARG). */
@@ -204,8 +204,8 @@ ups_status ups_register_scan(ups_context *ctx, const ups_geom *scan_g, const flo
  * no context, no allocation.  Same arguments (minus the context), numerics,
  * result and errors as ups_register_scan; it runs on the calling thread's
  * current device, and `stream` (NULL = the default stream) must belong to it.
- * Its scratch (both panoramas' ray tables and pyramids, the block partials
- * and the registration state, 3.6 MB) is a static array in device memory
+ * Its scratch (both panoramas' ray tables, the block partials and the
+ * registration state, 0.82 MB) is a static array in device memory
  * that each GPU holds from the library's first use until the process ends;
  * scan and keyframe are limited to 262144 pixels each (e.g. 128 x 2048):
  * larger ones return UPS_ERR_WORKSPACE.  All calls on one GPU share that

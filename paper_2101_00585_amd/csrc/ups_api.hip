@@ -160,12 +160,9 @@ ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels,
     c->max_pixels = max_pixels;
     c->max_batch = max_batch;
     c->max_batch_pixels = max_batch_pixels;
-    const int64_t pyr = (max_pixels * 21 + 63) / 64 + 64;
     c->max_partial_blocks = partial_stride(max_pixels / kBlock + 64);  // single registrations (batches own theirs)
     c->lut_capacity = (size_t)1 << 20;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = hipMalloc(&c->pyr_scan, pyr * sizeof(float4));
-    if (e == hipSuccess) e = hipMalloc(&c->pyr_kf, pyr * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(&c->tmp_surfel, max_pixels * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(&c->fill_key, max_pixels * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(c->fill_key, 0xFF, max_pixels * sizeof(unsigned long long));
@@ -186,8 +183,6 @@ ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels,
 void ups_context_destroy(ups_context *c) {
     if (!c) return;
     DeviceGuard dg(c->device);
-    (void)hipFree(c->pyr_scan);
-    (void)hipFree(c->pyr_kf);
     (void)hipFree(c->tmp_surfel);
     (void)hipFree(c->fill_key);
     (void)hipFree(c->partials);
@@ -256,19 +251,12 @@ static ups_status register_impl(ups_context *ctx, const ups_geom *scan_g, const 
     UPS_CHECK_HIP(dg.err);
     Inst I;
     memset(&I, 0, sizeof(I));
-    size_t off_s = 0, off_k = 0;
     for (int l = 0; l < p->levels; l++) {
         if ((st = device_geom(ctx, scan_g, l, (hipStream_t)stream, &I.sg[l])) != UPS_OK) return st;
         if ((st = device_geom(ctx, kf_g, l, (hipStream_t)stream, &I.kg[l])) != UPS_OK) return st;
-        if (l == 0) {
-            I.scan[0] = (const float4 *)scan_surfel_d;
-            I.kf[0] = (const float4 *)kf_surfel_d;
-        } else {
-            I.scan[l] = ctx->pyr_scan + off_s;
-            I.kf[l] = ctx->pyr_kf + off_k;
-            off_s += (size_t)I.sg[l].rows * I.sg[l].cols;
-            off_k += (size_t)I.kg[l].rows * I.kg[l].cols;
-        }
+        // every level is read from the level-0 images
+        I.scan[l] = (const float4 *)scan_surfel_d;
+        I.kf[l] = (const float4 *)kf_surfel_d;
     }
     I.state = ctx->state;
     I.partials = ctx->partials;

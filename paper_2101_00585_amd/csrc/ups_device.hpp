@@ -191,8 +191,11 @@ struct Gather {
 
 // Branch-free: every lane issues its three loads (lanes without a pixel read
 // pixel 0) and carries kf_index = -1.
+// kshift: 0 when kf is the level's own image; l when it is the level-0 image
+// read at every 2^l-th row and column (pixel (i, j) of level l at
+// (i cols_0 + j) 2^l with cols_0 = cols 2^l).
 __device__ __forceinline__ Gather scan_side(const DGeom &sg, float4 s2, float2 e, float2 ca, const DGeom &kg,
-                                            const float4 *__restrict__ kf, const Rt32 &T) {
+                                            const float4 *__restrict__ kf, const Rt32 &T, int kshift = 0) {
     Gather G;
     const bool sok = surfel_ok(sg, s2);
     const float3 u = make_float3(e.x * ca.x, e.x * ca.y, e.y);
@@ -203,7 +206,7 @@ __device__ __forceinline__ Gather scan_side(const DGeom &sg, float4 s2, float2 e
     const bool ok = project(kg, G.q, ki, kj) & sok;
     ki = ok ? ki : 0;
     kj = ok ? kj : 0;
-    const uint32_t idx = __umul24((uint32_t)ki, (uint32_t)kg.cols) + (uint32_t)kj;
+    const uint32_t idx = (__umul24((uint32_t)ki, (uint32_t)kg.cols << kshift) + (uint32_t)kj) << kshift;
     G.kf_index = ok ? (int)idx : -1;
     G.s1 = ldg_u(kf, idx);
     G.e = ldg_u(kg.lut_row, (uint32_t)ki << kg.lshift);
@@ -243,7 +246,8 @@ __device__ __forceinline__ float3 inv_transform(const Rt32 &T, float3 y) {
 }
 
 __device__ __forceinline__ Gather scan_side_world(const DGeom &sg, float4 s2, float2 e, float2 ca, const DGeom &kg,
-                                                  const float4 *__restrict__ kf, const Rt32 &T, const Rt32 &W) {
+                                                  const float4 *__restrict__ kf, const Rt32 &T, const Rt32 &W,
+                                                  int kshift = 0) {
     Gather G;
     G.kf_index = -1;
     if (!surfel_ok(sg, s2)) return G;
@@ -253,7 +257,7 @@ __device__ __forceinline__ Gather scan_side_world(const DGeom &sg, float4 s2, fl
     G.m = rotate(T, make_float3(s2.x, s2.y, s2.z));
     int ki, kj;
     if (!project(kg, inv_transform(W, G.q), ki, kj)) return G;
-    G.kf_index = ki * kg.cols + kj;
+    G.kf_index = (ki * (kg.cols << kshift) + kj) << kshift;
     G.s1 = ldg(kf, G.kf_index);
     G.e = ldg(kg.lut_row, ki * kg.stride);
     G.a = ldg(kg.lut_col, kj * kg.stride);

@@ -45,35 +45,6 @@ __device__ __forceinline__ void pyramid_from_level1(const DGeom *g, const float4
     if (levels > 3 && ((i | j) & 3) == 0) ((float4 *)img[3])[(i >> 2) * g[3].cols + (j >> 2)] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prepare_one(Inst I, const ups_pose *init, int levels) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t == 0) {
-        RegState S;
-        memset(&S, 0, sizeof(S));
-        if (I.world) {
-            // the scan's world pose = keyframe world pose * init, FP64
-            for (int a = 0; a < 3; a++) {
-                for (int c = 0; c < 3; c++)
-                    S.R[3 * a + c] = I.wR[3 * a] * init->R[c] + I.wR[3 * a + 1] * init->R[3 + c] +
-                                     I.wR[3 * a + 2] * init->R[6 + c];
-                S.t[a] = I.wR[3 * a] * init->t[0] + I.wR[3 * a + 1] * init->t[1] + I.wR[3 * a + 2] * init->t[2] +
-                         I.wt[a];
-            }
-        } else {
-            for (int k = 0; k < 9; k++) S.R[k] = init->R[k];
-            for (int k = 0; k < 3; k++) S.t[k] = init->t[k];
-        }
-        S.status = UPS_CONVERGED;
-        S.level_active = 1;
-        I.state[0] = S;
-    }
-    // pyramids of the scan (image 0) and the keyframe (image 1) from their level-1 pixels
-    if (levels < 2) return;
-    const int n0 = I.sg[1].rows * I.sg[1].cols;
-    if (t < n0) pyramid_from_level1(I.sg, I.scan, levels, t);
-    else if (t - n0 < I.kg[1].rows * I.kg[1].cols) pyramid_from_level1(I.kg, I.kf, levels, t - n0);
-}
-
 // Batch: blocks [0, init_blocks) initialise the states from init[k]; the
 // other blocks build the pyramids, one thread per level-1 pixel, found
 // through the prefix table of per-registration level-1 pixel counts (scan,
@@ -282,19 +253,12 @@ static ups_status launch_finish_one(int prec, const Inst &I, int parity, hipStre
     return UPS_OK;
 }
 
-static ups_status launch_collapse_one(int prec, int mode, const Inst &I, int parity, hipStream_t s) {
-    if (mode == MODE_ITER) {
-        UPS_DISPATCH_P(prec, hipLaunchKernelGGL((k_collapse_one<PP, 29>), dim3(1), dim3(kBlock), 0, s, I, parity))
-    } else {
-        UPS_DISPATCH_P(prec, hipLaunchKernelGGL((k_collapse_one<PP, 31>), dim3(1), dim3(kBlock), 0, s, I, parity))
-    }
+static ups_status launch_collapse_one(int prec, const Inst &I, int parity, hipStream_t s) {
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_collapse_one<PP>, dim3(1), dim3(kBlock), 0, s, I, parity))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
 
-// A registration: prepare (init + pyramids), the Gauss-Newton launches level
-// by level, the evaluation launch and the finish launch.  The descriptor
-// carries the state/partials scratch; pixels per thread follow pick_k_single.
 // One iteration or evaluation launch of a single registration: the variant
 // (world frame, IRLS, plain) selects the translation unit that holds it.
 static ups_status launch_one(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
@@ -310,6 +274,11 @@ static ups_status launch_one(int K, int prec, int mode, const Inst &I, const Ste
     return launch_icp_one_plain(K, prec, mode, I, a, blocks, s);
 }
 
+// A registration: the Gauss-Newton launches level by level (the first builds
+// the state from the start pose; each applies the previous launch's update),
+// the evaluation launch and the finish launch that writes the result.  Levels
+// are read from the level-0 images (no pyramid copies); the descriptor carries
+// the state / partials scratch; pixels per thread follow pick_k_single.
 ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_params &p, hipStream_t s) {
     Inst I = I0;
     int Ks[4] = {1, 1, 1, 1};
@@ -318,17 +287,13 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
         Ks[l] = pick_k_single(npix);
         I.nblocks[l] = (npix + kBlock * Ks[l] - 1) / (kBlock * Ks[l]);
     }
-    const int npre = p.levels > 1 ? I.sg[1].rows * I.sg[1].cols + I.kg[1].rows * I.kg[1].cols : 0;
-    const int pre_blocks = npre > 0 ? (npre + kBlock - 1) / kBlock : 1;
-    hipLaunchKernelGGL(k_prepare_one, dim3(pre_blocks), dim3(kBlock), 0, s, I, init, p.levels);
-    UPS_CHECK_HIP(hipGetLastError());
-
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.cos_theta = p.cos_theta_max;
     a.irls_delta = p.irls_delta;
     a.min_inliers = p.min_inliers;
     a.stop_norm = p.stop_update_norm;
+    a.init = init;
     int parity = 0;
     ups_status st;
     a.prev_level = -1;
@@ -339,13 +304,14 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
             a.parity = parity;
             a.first_of_level = it == 0;
             if ((st = launch_one(Ks[l], p.precision, MODE_ITER, I, a, I.nblocks[l], s)) != UPS_OK) return st;
+            a.init = nullptr;
             a.prev_level = l;
             parity ^= 1;
-            if (I.nblocks[l] > 256 && (st = launch_collapse_one(p.precision, MODE_ITER, I, parity, s)) != UPS_OK)
+            if (I.nblocks[l] > 256 && (st = launch_collapse_one(p.precision, I, parity, s)) != UPS_OK)
                 return st;
         }
     }
-    // evaluation at level 0: apply the last update, quality terms
+    // evaluation at level 0: apply the last update, quality terms; result
     a.level = 0;
     a.parity = parity;
     a.first_of_level = 0;
@@ -353,20 +319,17 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
     a.tau2 = a.d_max2;
     a.check_max_iters = (p.stop_update_norm > 0.0 && p.iters[0] > 0);
     if ((st = launch_one(Ks[0], p.precision, MODE_EVAL, I, a, I.nblocks[0], s)) != UPS_OK) return st;
-    parity ^= 1;
-    if (I.nblocks[0] > 256 && (st = launch_collapse_one(p.precision, MODE_EVAL, I, parity, s)) != UPS_OK) return st;
-    return launch_finish_one(p.precision, I, parity, s);
+    return launch_finish_one(p.precision, I, parity ^ 1, s);
 }
 
-// Normal equations at a fixed pose: prepare (pose only) + evaluation + finish.
+// Normal equations at a fixed pose: one evaluation launch that builds the
+// state from the pose, then the finish launch that writes the totals.
 ups_status launch_eval(const Inst &I0, const ups_pose *T, float d_max, float cos_theta, int precision,
                        hipStream_t s) {
     Inst I = I0;
     const int npix = I.sg[0].rows * I.sg[0].cols;
     const int K = pick_k_single(npix);
     I.nblocks[0] = (npix + kBlock * K - 1) / (kBlock * K);
-    hipLaunchKernelGGL(k_prepare_one, dim3(1), dim3(kBlock), 0, s, I, T, 1);
-    UPS_CHECK_HIP(hipGetLastError());
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.level = 0;
@@ -375,9 +338,9 @@ ups_status launch_eval(const Inst &I0, const ups_pose *T, float d_max, float cos
     a.d_max2 = d_max * d_max;
     a.tau2 = a.d_max2;
     a.cos_theta = cos_theta;
-    ups_status st = launch_one(K, precision, MODE_EVAL, I, a, I.nblocks[0], s);
+    a.init = T;
+    const ups_status st = launch_one(K, precision, MODE_EVAL, I, a, I.nblocks[0], s);
     if (st != UPS_OK) return st;
-    if (I.nblocks[0] > 256 && (st = launch_collapse_one(precision, MODE_EVAL, I, 1, s)) != UPS_OK) return st;
     return launch_finish_one(precision, I, 1, s);
 }
 

@@ -24,7 +24,9 @@ struct RegState {
     int skip;           // batches: the registration takes no part in this call (masked out)
 };
 
-// One registration as the kernels see it.
+// One registration as the kernels see it.  Batches read pyramid images of
+// each level (scan[l], kf[l]); single registrations (the fused kernels) read
+// level l straight from the level-0 images, every 2^l-th row and column.
 struct Inst {
     DGeom sg[4], kg[4];           // geometry of each pyramid level
     const float4 *scan[4], *kf[4];  // surfel images of each level (level 0 = caller's)
@@ -49,6 +51,7 @@ struct StepArgs {
     int min_inliers;
     double stop_norm;
     int kpt;  // MODE_SCHED: pixels per thread of this tile (<= the kernel's K, a multiple of its pixel groups)
+    const ups_pose *init;  // single registrations: the first launch builds the state from this start pose
     int reverse_tiles;  // debug: workgroups take the tiles in reverse order (set by the launchers)
 };
 

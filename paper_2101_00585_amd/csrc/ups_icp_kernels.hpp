@@ -600,6 +600,26 @@ __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nbloc
 // WORLD: the world-frame variant (state pose = the scan's world pose).
 // IRLS: the absolute-value objective of Equation 1, each inlier's terms
 // weighted by 1 / max(|r|, a.irls_delta).
+// The state a registration starts from: the start pose (world-frame variant:
+// the scan's world pose, keyframe world pose x start pose, in FP64), status
+// CONVERGED, the first level active, no iterations run.
+__device__ __forceinline__ void init_state(const Inst &I, const ups_pose *init, RegState &S) {
+    memset(&S, 0, sizeof(S));
+    if (I.world) {
+        for (int a = 0; a < 3; a++) {
+            for (int c = 0; c < 3; c++)
+                S.R[3 * a + c] =
+                    I.wR[3 * a] * init->R[c] + I.wR[3 * a + 1] * init->R[3 + c] + I.wR[3 * a + 2] * init->R[6 + c];
+            S.t[a] = I.wR[3 * a] * init->t[0] + I.wR[3 * a + 1] * init->t[1] + I.wR[3 * a + 2] * init->t[2] + I.wt[a];
+        }
+    } else {
+        for (int k = 0; k < 9; k++) S.R[k] = init->R[k];
+        for (int k = 0; k < 3; k++) S.t[k] = init->t[k];
+    }
+    S.status = UPS_CONVERGED;
+    S.level_active = 1;
+}
+
 // LDS workspace of one block's tile (one per kernel, whichever modes it runs).
 template <typename Acc>
 struct IcpShared {
@@ -626,9 +646,23 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     Acc(&tot)[32] = sh.tot;
     int &active = sh.active;
     const DGeom sg = I.sg[l], kg = I.kg[l];
-    const float4 *__restrict__ scan = I.scan[l];
-    const float4 *__restrict__ kf = I.kf[l];
+    // single registrations (FUSED) read level l from the level-0 images, every
+    // 2^l-th row and column; batches read the level's pyramid images
+    const int ish = FUSED ? l : 0;
+    const float4 *__restrict__ scan = I.scan[FUSED ? 0 : l];
+    const float4 *__restrict__ kf = I.kf[FUSED ? 0 : l];
     const int npix = sg.rows * sg.cols;
+    // scan image index of level-l pixel q, whose wavefront starts at pixel qw
+    // (wave-uniform) and whose column is jcol; past the last pixel: clamped
+    // into the image
+    auto scan_index = [&](int q, int qw, int jcol) -> uint32_t {
+        if constexpr (FUSED) {
+            const int row = __builtin_amdgcn_readfirstlane(min(qw, npix - 1)) / sg.cols;
+            return (uint32_t)((row * (sg.cols << ish) + jcol) << ish);
+        } else {
+            return (uint32_t)min(q, npix - 1);
+        }
+    };
     // pixels per thread of this tile: K, or fewer for a scheduled tile
     const int KL = (MODE == MODE_SCHED) ? a.kpt : K;
     const int base = tile * (kBlock * KL);
@@ -651,7 +685,7 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     for (int u = 0; u < P; u++) {
         if (u == 0) jc[u] = (base + tid) % sg.cols;
         else jc[u] = jc[u - 1] + col_step >= sg.cols ? jc[u - 1] + col_step - sg.cols : jc[u - 1] + col_step;
-        nx[u] = ldg_u(scan, (uint32_t)min(base + u * kBlock + tid, npix - 1));
+        nx[u] = ldg_u(scan, scan_index(base + u * kBlock + tid, pw0 + u * kBlock, jc[u]));
         na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
     }
     if (!FUSED) {
@@ -671,7 +705,9 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         if ((tid & 7) == 0 && (tid >> 3) < 29) tot[tid >> 3] = ptot;
         __syncthreads();
         // ---- 0. the previous launch's update, solved identically by every block
+        // (the first launch of a call: the state from the start pose)
         if (tid == 0) {
+            if (a.init) init_state(I, a.init, S);
             if (S.pending && !S.stop) gn_step<Acc>(a, tot, S);
             S.pending = 0;
             if (MODE == MODE_ITER && a.first_of_level) S.level_active = 1;
@@ -723,8 +759,8 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
                 sw[u] = s2.w;
                 const int i = min(pw + u * kBlock, npix - 1) / sg.cols;
                 const float2 e = lds_uniform(sg.lut_row, i * sg.stride);
-                if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk);
-                else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T);
+                if constexpr (WORLD) G[u] = scan_side_world(sg, s2, e, na[u], kg, kf, T, Wk, ish);
+                else G[u] = scan_side(sg, s2, e, na[u], kg, kf, T, ish);
                 // keep the consumers of these gathers below the next pixel's scan side
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -735,7 +771,8 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
                     jc[u] += more ? P * col_step : 0;
                     jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
                     jc[u] = jc[u] >= sg.cols ? jc[u] - sg.cols : jc[u];
-                    nx[u] = ldg_u(scan, (uint32_t)min(base + (more ? k + P + u : k + u) * kBlock + tid, npix - 1));
+                    const int ku = more ? k + P + u : k + u;
+                    nx[u] = ldg_u(scan, scan_index(base + ku * kBlock + tid, pw + (ku - k) * kBlock, jc[u]));
                     na[u] = ldg_u(sg.lut_col, (uint32_t)jc[u] << sg.lshift);
                 }
             }
@@ -897,50 +934,59 @@ __device__ __forceinline__ void finish_block(const Inst &I, int parity, ups_icp_
     if (S->skip) return;  // masked out of this batch call: the result is left as it was
     reduce_partials<31, Acc>(I.partials + (size_t)parity * I.pstride * kPartialStride, I.pstride,
                              npartials_of(I.nblocks[0]), tot);
-    if (threadIdx.x != 0) return;
     write_result<Acc>(I, S, tot, res, neq);
 }
 
 // The result of a registration (quality at the final pose from the 31
 // evaluation totals, plus the state's pose, status, iteration counts and last
-// step norm), or its normal equations.
+// step norm), or its normal equations; called by every thread of the block,
+// each writing a few of the fields.
 template <typename Acc>
 __device__ void write_result(const Inst &I, const RegState *S, const Acc *tot, ups_icp_result *res,
                              ups_normal_eq *neq) {
-    const double n_in = (double)tot[28], n_valid = (double)tot[29];
-    if (res) {
-        ups_icp_result *r = res;
+    const int t = threadIdx.x;
+    if (t < 27) {
+        const double v = (double)tot[t];
+        if (res) (t < 21 ? res->JtJ[t] : res->Jtr[t - 21]) = v;
+        if (neq) (t < 21 ? neq->JtJ[t] : neq->Jtr[t - 21]) = v;
+    }
+    if (res && t >= 32 && t < 44) {
+        const int k = t - 32;  // entry of the pose: R row-major (0..8), then t (9..11)
+        double v;
         if (I.world) {
             // scan -> keyframe = (keyframe world pose)^-1 (scan world pose), FP64
-            for (int a = 0; a < 3; a++) {
-                for (int c = 0; c < 3; c++)
-                    r->T.R[3 * a + c] = I.wR[a] * S->R[c] + I.wR[3 + a] * S->R[3 + c] + I.wR[6 + a] * S->R[6 + c];
-                r->T.t[a] = I.wR[a] * (S->t[0] - I.wt[0]) + I.wR[3 + a] * (S->t[1] - I.wt[1]) +
-                            I.wR[6 + a] * (S->t[2] - I.wt[2]);
+            if (k < 9) {
+                const int a = k / 3, c = k - 3 * (k / 3);
+                v = I.wR[a] * S->R[c] + I.wR[3 + a] * S->R[3 + c] + I.wR[6 + a] * S->R[6 + c];
+            } else {
+                const int a = k - 9;
+                v = I.wR[a] * (S->t[0] - I.wt[0]) + I.wR[3 + a] * (S->t[1] - I.wt[1]) +
+                    I.wR[6 + a] * (S->t[2] - I.wt[2]);
             }
         } else {
-            for (int k = 0; k < 9; k++) r->T.R[k] = S->R[k];
-            for (int k = 0; k < 3; k++) r->T.t[k] = S->t[k];
+            v = k < 9 ? S->R[k] : S->t[k - 9];
         }
-        r->status = S->status;
-        r->iters_run = S->iters_run;
-        for (int k = 0; k < 4; k++) r->level_iters[k] = S->level_iters[k];
-        r->last_update_norm = S->last_norm;
-        for (int k = 0; k < 21; k++) r->JtJ[k] = (double)tot[k];
-        for (int k = 0; k < 6; k++) r->Jtr[k] = (double)tot[21 + k];
-        r->inliers = (int64_t)n_in;
-        r->valid = (int64_t)n_valid;
-        r->inlier_ratio = n_valid > 0 ? n_in / n_valid : 0.0;
-        r->rms = n_in > 0 ? sqrt((double)tot[27] / n_in) : 0.0;
-        r->trunc_cost = (double)tot[30];
+        if (k < 9) res->T.R[k] = v;
+        else res->T.t[k - 9] = v;
     }
-    if (neq) {
-        ups_normal_eq *q = neq;
-        for (int k = 0; k < 21; k++) q->JtJ[k] = (double)tot[k];
-        for (int k = 0; k < 6; k++) q->Jtr[k] = (double)tot[21 + k];
-        q->sum_r2 = (double)tot[27];
-        q->inliers = (int64_t)n_in;
-        q->valid = (int64_t)n_valid;
+    if (t == 64) {
+        const double n_in = (double)tot[28], n_valid = (double)tot[29];
+        if (res) {
+            res->status = S->status;
+            res->iters_run = S->iters_run;
+            for (int k = 0; k < 4; k++) res->level_iters[k] = S->level_iters[k];
+            res->last_update_norm = S->last_norm;
+            res->inliers = (int64_t)n_in;
+            res->valid = (int64_t)n_valid;
+            res->inlier_ratio = n_valid > 0 ? n_in / n_valid : 0.0;
+            res->rms = n_in > 0 ? sqrt((double)tot[27] / n_in) : 0.0;
+            res->trunc_cost = (double)tot[30];
+        }
+        if (neq) {
+            neq->sum_r2 = (double)tot[27];
+            neq->inliers = (int64_t)n_in;
+            neq->valid = (int64_t)n_valid;
+        }
     }
 }
 
@@ -955,14 +1001,15 @@ __global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict_
     finish_block<PREC>(insts[blockIdx.x], parity, results + blockIdx.x, nullptr);
 }
 
-// More than 256 partials: fold them into one before the next launch reads
-// them (keeps the per-block read of step 0 bounded).
-template <int PREC, int NV>
+// More than 256 iteration partials: fold them into one before the next
+// launch reads them (keeps the per-block read of step 0 bounded).
+template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
+    constexpr int NV = 29;
     using Acc = AccOf<PREC>;
     RegState *S = I.state + parity;
     double *part = I.partials + (size_t)parity * I.pstride * kPartialStride;
-    if (NV == 29 && !S->pending) return;
+    if (!S->pending) return;
     // the 8 threads of value v read only row v, and have read all of it
     // before the group's sum exists: the total can overwrite block 0's entry
     const Acc t = sum_partials<NV, Acc>(part, I.pstride, S->npartials);
@@ -976,20 +1023,20 @@ __global__ __launch_bounds__(kBlock) void k_collapse_one(Inst I, int parity) {
 // partials through agent-coherent loads: thread g of the group adds partials
 // g, g + 8, ... in order, then oct_sum; the totals into tot (LDS), visible
 // to the whole block on return.  The same sums whatever the blocks' order of
-// arrival.
+// arrival.  All 32 loads of a chunk of 256 partials are issued before the
+// first is added (one memory round trip per chunk).
 template <int NV, typename Acc>
 __device__ __forceinline__ void reduce_partials_coh(const double *part, int pstride, int n, Acc *tot) {
     const int v = min((int)(threadIdx.x >> 3), NV - 1), g = threadIdx.x & 7;
     const double *pv = part + (size_t)v * pstride;
     Acc t = 0;
-    for (int b0 = 0; b0 < n; b0 += 64) {
-        // eight loads in flight per thread; an index past the last partial is
-        // clamped and its value unused
-        double x[8];
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        // an index past the last partial is clamped and its value unused
+        double x[32];
 #pragma unroll
-        for (int q = 0; q < 8; q++) x[q] = ld_coh_d(pv + min(b0 + g + 8 * q, n - 1));
+        for (int q = 0; q < 32; q++) x[q] = ld_coh_d(pv + min(b0 + g + 8 * q, n - 1));
 #pragma unroll
-        for (int q = 0; q < 8; q++) t += (b0 + g + 8 * q < n) ? (Acc)x[q] : Acc(0);
+        for (int q = 0; q < 32; q++) t += (b0 + g + 8 * q < n) ? (Acc)x[q] : Acc(0);
     }
     t = oct_sum<Acc>(t);
     if ((threadIdx.x & 7) == 0 && (threadIdx.x >> 3) < NV) tot[threadIdx.x >> 3] = t;

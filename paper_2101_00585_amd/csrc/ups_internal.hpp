@@ -51,8 +51,6 @@ struct ups_context {
     int32_t max_batch = 0;
     int64_t max_batch_pixels = 0;
     // scratch
-    float4 *pyr_scan = nullptr;  // levels 1..3 of a scan, max_pixels * 21/64
-    float4 *pyr_kf = nullptr;
     float4 *tmp_surfel = nullptr;  // a-trous ping-pong, max_pixels
     unsigned long long *fill_key = nullptr;  // fuse fill pass, max_pixels
     double *partials = nullptr;              // [2][kPartialStride][max_partial_blocks] block partials

@@ -1,9 +1,8 @@
 // ups_register_scan_noalloc: the registration of ups_register_scan (Section
 // III-B) for callers that cannot allocate device memory.  No context: the
 // scratch the registration kernels need beyond their inputs and outputs --
-// both panoramas' ray tables, the scan and keyframe pyramids, the block
-// partials and the two state slots -- lives in one static device array per
-// GPU, `scratch`, of kScratchBytes.  Host code never passes the array's name
+// both panoramas' ray tables, the block partials and the two state slots --
+// lives in one static device array per GPU, `scratch`, of kScratchBytes.  Host code never passes the array's name
 // to a kernel (on the host it is only a stand-in for the symbol): the device
 // address of each GPU's copy is looked up once per device with
 // hipGetSymbolAddress and kept in g_scratch[device].
@@ -27,24 +26,19 @@ constexpr int64_t kMaxPixels = 262144;
 // Ray-table entries per geometry: rows + cols of any accepted geometry of at
 // most kMaxPixels pixels (rows >= 2, cols <= 16384).
 constexpr int64_t kMaxLut = 16384 + kMaxPixels / 16384;
-// Pyramid levels 1..3 of one panorama: at most 21/64 of its pixels.
-constexpr int64_t kPyrFloat4 = (kMaxPixels * 21 + 63) / 64 + 64;
 // Blocks of the widest launch (pick_k_single keeps it at or below 256; the
 // context sizes its partials the same way from the pixel count).
 constexpr int64_t kPstride = (kMaxPixels / kBlock + 64 + 15) / 16 * 16;
 
 constexpr int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 constexpr int64_t kLutBytes = align256(kMaxLut * (int64_t)sizeof(float2));
-constexpr int64_t kPyrBytes = align256(kPyrFloat4 * (int64_t)sizeof(float4));
 constexpr int64_t kPartialBytes = align256(2 * kPartialStride * kPstride * (int64_t)sizeof(double));
 constexpr int64_t kStateBytes = align256(2 * (int64_t)sizeof(RegState));
 
 // byte offsets of the sections
 constexpr int64_t kOffLutScan = 0;
 constexpr int64_t kOffLutKf = kOffLutScan + kLutBytes;
-constexpr int64_t kOffPyrScan = kOffLutKf + kLutBytes;
-constexpr int64_t kOffPyrKf = kOffPyrScan + kPyrBytes;
-constexpr int64_t kOffPartials = kOffPyrKf + kPyrBytes;
+constexpr int64_t kOffPartials = kOffLutKf + kLutBytes;
 constexpr int64_t kOffState = kOffPartials + kPartialBytes;
 constexpr int64_t kScratchBytes = kOffState + kStateBytes;
 static_assert(kScratchBytes <= (4 << 20), "the static scratch stays within 4 MiB");
@@ -140,20 +134,12 @@ extern "C" ups_status ups_register_scan_noalloc(const ups_geom *scan_g, const fl
 
     Inst I;
     memset(&I, 0, sizeof(I));
-    size_t off_s = 0, off_k = 0;
-    float4 *pyr_s = (float4 *)(base + kOffPyrScan), *pyr_k = (float4 *)(base + kOffPyrKf);
     for (int l = 0; l < p->levels; l++) {
         I.sg[l] = geom_view(scan_g, l, lut_s, lut_s + scan_g->rows);
         I.kg[l] = geom_view(kf_g, l, lut_k, lut_k + kf_g->rows);
-        if (l == 0) {
-            I.scan[0] = (const float4 *)scan_surfel_d;
-            I.kf[0] = (const float4 *)kf_surfel_d;
-        } else {
-            I.scan[l] = pyr_s + off_s;
-            I.kf[l] = pyr_k + off_k;
-            off_s += (size_t)I.sg[l].rows * I.sg[l].cols;
-            off_k += (size_t)I.kg[l].rows * I.kg[l].cols;
-        }
+        // every level is read from the level-0 images
+        I.scan[l] = (const float4 *)scan_surfel_d;
+        I.kf[l] = (const float4 *)kf_surfel_d;
     }
     I.state = (RegState *)(base + kOffState);
     I.partials = (double *)(base + kOffPartials);
