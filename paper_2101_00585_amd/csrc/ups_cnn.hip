@@ -2,11 +2,12 @@
 // network (BF16 operands on the matrix cores, FP32 accumulation).
 //
 // Every convolution pass is an implicit GEMM on one tile engine: a 256-thread
-// block computes a 64 x 64 tile of C = A B, staging 64 x 16 slices of A and B
-// through LDS as bfloat16 and issuing v_mfma_f32_16x16x16_bf16 (each wavefront
-// owns a 32 x 32 quarter: 2 x 2 MFMA tiles).  The K loop takes slices of KB
-// (32, or 16 when K is at most 32) and loads the next slice into registers
-// while the matrix cores work on the current one.  Operand loaders gather A and B
+// block computes a 64 x 64 tile of C = A B, staging 64 x KB slices of A and B
+// through LDS as bfloat16 and issuing gfx950's v_mfma_f32_16x16x32_bf16 (each
+// wavefront owns a 32 x 32 quarter: 2 x 2 MFMA tiles, 32 k per instruction;
+// v_mfma_f32_16x16x16_bf16 when K is at most 32 and the slice is 16 wide).
+// The K loop loads the next slice into registers while the matrix cores work
+// on the current one.  Operand loaders gather A and B
 // straight from the NHWC activations, so no im2col buffer exists:
 //   forward          C[pixel_out][cout] = X_col[pixel_out][(tap,ci)] W[(tap,ci)][cout]
 //   backward (data)  C[pixel_in][ci]    = G_col[pixel_in][(tap,co)]  W[(tap,ci)][co]^T
@@ -20,6 +21,7 @@
 namespace ups {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // round to nearest even
@@ -40,7 +42,11 @@ constexpr int kSplitAlign = 16;                              // weight-gradient 
 template <int KB = 32, class LA, class LB, class ST>
 __device__ __forceinline__ void mfma_tile(const LA &la, const LB &lb, const ST &st, int m0, int n0, int M, int N,
                                           int k_begin, int k_end) {
-    constexpr int kLP = KB + 4;  // LDS row pitch (elements), padded to spread the rows over the banks
+    // 32-wide k chunks on the 16x16x32 instruction when the slice holds them
+    constexpr bool kX32 = KB % 32 == 0;
+    // LDS row pitch (elements), padded to spread the rows over the banks and
+    // keeping each row 16-byte aligned for the 8-element fragment loads
+    constexpr int kLP = kX32 ? KB + 8 : KB + 4;
     constexpr int kQ = KB / 16;  // k quads per thread and operand in one slice
     __shared__ __align__(16) uint16_t As[kBM * kLP];
     __shared__ __align__(16) uint16_t Bs[kBN * kLP];
@@ -72,22 +78,41 @@ __device__ __forceinline__ void mfma_tile(const LA &la, const LB &lb, const ST &
         __syncthreads();
         // the next slice's loads are in flight while this slice is multiplied
         if (k0 + KB < k_end) fetch(k0 + KB);
-        // 16-wide chunks of the slice in ascending k: the same accumulation
-        // order as a loop over 16-wide slices
+        // chunks of the slice in ascending k.  Lane l carries row (A) or
+        // column (B) l % 16 and the chunk's k = w (l / 16) .. w (l / 16) + w-1
+        // (w = 8 or 4 elements): the same k in the same slot of both operands
+        if constexpr (kX32) {
 #pragma unroll
-        for (int kc = 0; kc < kQ; kc++) {
-            bf16x4 fa[2], fb[2];
+            for (int kc = 0; kc < KB / 32; kc++) {
+                bf16x8 fa[2], fb[2];
 #pragma unroll
-            for (int i = 0; i < 2; i++)
-                fa[i] = *(const bf16x4 *)&As[(32 * wm + 16 * i + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
-#pragma unroll
-            for (int j = 0; j < 2; j++)
-                fb[j] = *(const bf16x4 *)&Bs[(32 * wn + 16 * j + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
-#pragma unroll
-            for (int i = 0; i < 2; i++)
+                for (int i = 0; i < 2; i++)
+                    fa[i] = *(const bf16x8 *)&As[(32 * wm + 16 * i + (lane & 15)) * kLP + 32 * kc + 8 * (lane >> 4)];
 #pragma unroll
                 for (int j = 0; j < 2; j++)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                    fb[j] = *(const bf16x8 *)&Bs[(32 * wn + 16 * j + (lane & 15)) * kLP + 32 * kc + 8 * (lane >> 4)];
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+#pragma unroll
+                    for (int j = 0; j < 2; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < kQ; kc++) {
+                bf16x4 fa[2], fb[2];
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+                    fa[i] = *(const bf16x4 *)&As[(32 * wm + 16 * i + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 2; j++)
+                    fb[j] = *(const bf16x4 *)&Bs[(32 * wn + 16 * j + (lane & 15)) * kLP + 16 * kc + 4 * (lane >> 4)];
+#pragma unroll
+                for (int i = 0; i < 2; i++)
+#pragma unroll
+                    for (int j = 0; j < 2; j++)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
