@@ -399,11 +399,56 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
 
 namespace {
 
-// The launch sequence of a batch call; with a mask only the masked-in
-// registrations run (their pyramids left by the previous call are reused),
-// through the batch's Compact list of them.
-ups_status register_batch_launches(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
-                               hipStream_t s) {
+// The launch sequence of a batch call over every registration: prepare, then
+// one launch per Gauss-Newton iteration in which each block first applies
+// its registration's pending update (state and partials in ping-pong slots),
+// the evaluation launch (which applies the last update) and the finish.
+ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_result *results_d, hipStream_t s) {
+    ups_status st;
+    const ups_icp_params &p = b->p;
+    const int n = b->n;
+    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, nullptr, s)) !=
+        UPS_OK)
+        return st;
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cos_theta = p.cos_theta_max;
+    a.irls_delta = p.irls_delta;
+    a.min_inliers = p.min_inliers;
+    a.stop_norm = p.stop_update_norm;
+    a.prev_level = -1;
+    int parity = 0;
+    for (int l = p.levels - 1; l >= 0; l--) {
+        a.level = l;
+        a.d_max2 = p.d_max[l] * p.d_max[l];
+        for (int it = 0; it < p.iters[l]; it++) {
+            a.parity = parity;
+            a.first_of_level = it == 0;
+            if ((st = launch_icp_batch(b->K[l], p.precision, MODE_ITER, b->d_inst, b->d_tile_start + l * (n + 1), n,
+                                       a, b->total_tiles[l], s, true)) != UPS_OK)
+                return st;
+            a.prev_level = l;
+            parity ^= 1;
+        }
+    }
+    a.level = 0;
+    a.parity = parity;
+    a.first_of_level = 0;
+    a.d_max2 = p.d_max[0] * p.d_max[0];
+    a.tau2 = a.d_max2;
+    a.check_max_iters = (p.stop_update_norm > 0.0 && p.iters[0] > 0);
+    if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0],
+                               s, true)) != UPS_OK)
+        return st;
+    return launch_finish_batch(p.precision, b->d_inst, n, parity ^ 1, results_d, s);
+}
+
+// A call over the masked-in registrations (the fallback): their pyramids left
+// by the previous call are reused, and the launches go through the batch's
+// Compact list of them, with one solve launch per iteration (pose in state
+// slot 0).
+ups_status register_batch_subset(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
+                                 hipStream_t s) {
     ups_status st;
     const ups_icp_params &p = b->p;
     const int n = b->n;
@@ -424,33 +469,24 @@ ups_status register_batch_launches(ups_batch *b, const ups_pose *init_d, const u
         const int l = seq[q];
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
-        if (mask)
-            st = launch_icp_batch_list(b->K[l], p.precision, MODE_ITER, b->d_inst, b->comp, b->comp_list,
-                                       b->comp_start + l * (n + 1), n, a, std::min(b->total_tiles[l], kListBlocks), s);
-        else
-            st = launch_icp_batch(b->K[l], p.precision, MODE_ITER, b->d_inst, b->d_tile_start + l * (n + 1), n, a,
-                                  b->total_tiles[l], s);
-        if (st != UPS_OK) return st;
+        if ((st = launch_icp_batch_list(b->K[l], p.precision, MODE_ITER, b->d_inst, b->comp, b->comp_list,
+                                        b->comp_start + l * (n + 1), n, a, std::min(b->total_tiles[l], kListBlocks),
+                                        s)) != UPS_OK)
+            return st;
         StepArgs sa = a;
         sa.prev_level = l;
         sa.first_of_level = (q + 1 < seq.size() && seq[q + 1] != l);
         sa.check_max_iters = (q + 1 == seq.size() && l == 0 && p.stop_update_norm > 0.0);
-        if (mask)
-            st = launch_solve_batch_list(p.precision, b->d_inst, b->comp, b->comp_list, std::min(n, kListSolveBlocks),
-                                         sa, s);
-        else
-            st = launch_solve_batch(p.precision, b->d_inst, n, sa, s);
-        if (st != UPS_OK) return st;
+        if ((st = launch_solve_batch_list(p.precision, b->d_inst, b->comp, b->comp_list, std::min(n, kListSolveBlocks),
+                                          sa, s)) != UPS_OK)
+            return st;
     }
     a.level = 0;
     a.d_max2 = p.d_max[0] * p.d_max[0];
     a.tau2 = a.d_max2;
-    if (mask)
-        st = launch_icp_batch_list(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->comp, b->comp_list, b->comp_start,
-                                   n, a, std::min(b->total_tiles[0], kListBlocks), s);
-    else
-        st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0], s);
-    if (st != UPS_OK) return st;
+    if ((st = launch_icp_batch_list(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->comp, b->comp_list, b->comp_start, n,
+                                    a, std::min(b->total_tiles[0], kListBlocks), s)) != UPS_OK)
+        return st;
     return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
 }
 
@@ -510,7 +546,8 @@ ups_status register_batch_persistent(ups_batch *b, const ups_pose *init_d, const
 ups_status register_batch_impl(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
                                hipStream_t s) {
     if (b->scheduler == UPS_SCHED_PERSISTENT) return register_batch_persistent(b, init_d, mask, results_d, s);
-    return register_batch_launches(b, init_d, mask, results_d, s);
+    if (mask) return register_batch_subset(b, init_d, mask, results_d, s);
+    return register_batch_fused(b, init_d, results_d, s);
 }
 
 }  // namespace

@@ -129,8 +129,13 @@ ups_status launch_eval(const Inst &I, const ups_pose *T, float d_max, float cos_
 // instantiation themselves when a.irls_delta > 0; single registrations go
 // through launch_register / launch_eval.  Each variant lives in its own
 // translation unit (ups_icp_iter_*.hip).
+// fused: the batch's main loop (each block applies its registration's pending
+// update, state and partials in the ping-pong slots of a.parity); otherwise the
+// pose is in state slot 0.
 ups_status launch_icp_batch(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
-                            const StepArgs &a, int blocks, hipStream_t s);
+                            const StepArgs &a, int blocks, hipStream_t s, bool fused = false);
+ups_status launch_icp_batch_fused(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
+                                  const StepArgs &a, int blocks, hipStream_t s);
 ups_status launch_icp_one_plain(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
                                 hipStream_t s);
 ups_status launch_icp_one_world(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
@@ -138,7 +143,7 @@ ups_status launch_icp_one_world(int K, int prec, int mode, const Inst &I, const 
 ups_status launch_icp_one_irls(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
                                hipStream_t s);
 ups_status launch_icp_batch_irls(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
-                                 const StepArgs &a, int blocks, hipStream_t s);
+                                 const StepArgs &a, int blocks, hipStream_t s, bool fused);
 ups_status launch_icp_batch_list_irls(int K, int prec, int mode, const Inst *insts, const Compact *hdr,
                                       const int *list, const int *start_l, int n, const StepArgs &a, int blocks,
                                       hipStream_t s);
@@ -151,7 +156,6 @@ ups_status launch_icp_persistent(int K, int prec, const SchedArgs &A, int blocks
 int persistent_grid(int K, int prec, bool irls);
 // pixels per thread the persistent kernel is instantiated for
 bool persistent_k_supported(int K);
-ups_status launch_solve_batch(int prec, const Inst *insts, int n, const StepArgs &a, hipStream_t s);
 ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
                                    const StepArgs &a, hipStream_t s);
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,

@@ -30,23 +30,27 @@ ups_status launch_icp_one_irls(int K, int prec, int mode, const Inst &I, const S
     return UPS_OK;
 }
 
-template <int K>
+template <int K, bool FUSED>
 static void launch_batch_t(int mode, const Inst *insts, const int *tile_start, int n, const StepArgs &a0, int blocks,
                            hipStream_t s) {
     const StepArgs a = with_tile_order(a0);
     constexpr int P = UPS_PREC_KAHAN_F64;
     if (mode == MODE_ITER)
-        hipLaunchKernelGGL((k_icp_batch<K, P, MODE_ITER, true>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
-                           n, a);
+        hipLaunchKernelGGL((k_icp_batch<K, P, MODE_ITER, true, FUSED>), dim3(blocks), dim3(kBlock), 0, s, insts,
+                           tile_start, n, a);
     else
-        hipLaunchKernelGGL((k_icp_batch<K, P, MODE_EVAL, true>), dim3(blocks), dim3(kBlock), 0, s, insts, tile_start,
-                           n, a);
+        hipLaunchKernelGGL((k_icp_batch<K, P, MODE_EVAL, true, FUSED>), dim3(blocks), dim3(kBlock), 0, s, insts,
+                           tile_start, n, a);
 }
 
 ups_status launch_icp_batch_irls(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
-                                 const StepArgs &a, int blocks, hipStream_t s) {
+                                 const StepArgs &a, int blocks, hipStream_t s, bool fused) {
     if (!irls_precision_ok(prec)) return UPS_ERR_INVALID_ARG;
-    UPS_DISPATCH_K(K, launch_batch_t<KK>(mode, insts, tile_start, n, a, blocks, s))
+    if (fused) {
+        UPS_DISPATCH_K(K, (launch_batch_t<KK, true>(mode, insts, tile_start, n, a, blocks, s)))
+    } else {
+        UPS_DISPATCH_K(K, (launch_batch_t<KK, false>(mode, insts, tile_start, n, a, blocks, s)))
+    }
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

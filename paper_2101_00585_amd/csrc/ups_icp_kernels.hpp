@@ -594,9 +594,12 @@ __device__ void gn_step_wave(const StepArgs &a, const T *tot, RegState &S) {
 __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nblocks > 256 ? 1 : nblocks; }
 
 // FUSED: the block first applies the previous launch's update itself (step 0
-// above; single registrations).  Otherwise (batches) a separate one-block-per-
-// registration launch has already applied it and left the pose, and whether
-// this launch has work for the registration, in state slot 0.
+// above; single registrations and the batch's main loop), with the state and
+// partials in ping-pong slots (a.parity).  Otherwise (the batch's subset and
+// scheduled paths) another launch has already applied it and left the pose,
+// and whether this launch has work for the registration, in state slot 0.
+// STRIDED: level l is read from the level-0 images, every 2^l-th row and
+// column (single registrations); otherwise from the level's pyramid images.
 // WORLD: the world-frame variant (state pose = the scan's world pose).
 // IRLS: the absolute-value objective of Equation 1, each inlier's terms
 // weighted by 1 / max(|r|, a.irls_delta).
@@ -630,7 +633,7 @@ struct IcpShared {
     int job[8];  // persistent scheduler: ticket's registration and tile, last-arriver flag, spare, job (4 words)
 };
 
-template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS>
+template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS, bool STRIDED = FUSED>
 __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int tile, IcpShared<AccOf<PREC>> &sh) {
     constexpr int NV = (MODE == MODE_EVAL) ? 31 : 29;  // EVAL adds valid count and truncated cost
     using Acc = AccOf<PREC>;
@@ -646,17 +649,15 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     Acc(&tot)[32] = sh.tot;
     int &active = sh.active;
     const DGeom sg = I.sg[l], kg = I.kg[l];
-    // single registrations (FUSED) read level l from the level-0 images, every
-    // 2^l-th row and column; batches read the level's pyramid images
-    const int ish = FUSED ? l : 0;
-    const float4 *__restrict__ scan = I.scan[FUSED ? 0 : l];
-    const float4 *__restrict__ kf = I.kf[FUSED ? 0 : l];
+    const int ish = STRIDED ? l : 0;
+    const float4 *__restrict__ scan = I.scan[STRIDED ? 0 : l];
+    const float4 *__restrict__ kf = I.kf[STRIDED ? 0 : l];
     const int npix = sg.rows * sg.cols;
     // scan image index of level-l pixel q, whose wavefront starts at pixel qw
     // (wave-uniform) and whose column is jcol; past the last pixel: clamped
     // into the image
     auto scan_index = [&](int q, int qw, int jcol) -> uint32_t {
-        if constexpr (FUSED) {
+        if constexpr (STRIDED) {
             const int row = __builtin_amdgcn_readfirstlane(min(qw, npix - 1)) / sg.cols;
             return (uint32_t)((row * (sg.cols << ish) + jcol) << ish);
         } else {
@@ -821,10 +822,10 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     }
 }
 
-template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS>
+template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS, bool STRIDED = FUSED>
 __device__ __forceinline__ void icp_block(const Inst &I, const StepArgs &a, int tile) {
     __shared__ IcpShared<AccOf<PREC>> sh;
-    icp_tile<K, PREC, MODE, FUSED, WORLD, IRLS>(I, a, tile, sh);
+    icp_tile<K, PREC, MODE, FUSED, WORLD, IRLS, STRIDED>(I, a, tile, sh);
 }
 
 // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), and
@@ -845,8 +846,10 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 }
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix
-// table of tile counts (tile_start[n] = total blocks).
-template <int K, int PREC, int MODE, bool IRLS>
+// table of tile counts (tile_start[n] = total blocks).  FUSED: each block
+// first applies its registration's pending update (the batch's main loop);
+// otherwise slot 0 holds the pose (the subset and scheduled paths, timing).
+template <int K, int PREC, int MODE, bool IRLS, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
                                                       const int *__restrict__ tile_start, int n, StepArgs a) {
     const int b = xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles);
@@ -856,7 +859,7 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ i
         if (tile_start[mid] <= b) lo = mid;
         else hi = mid;
     }
-    icp_block<K, PREC, MODE, false, false, IRLS>(insts[lo], a, b - tile_start[lo]);
+    icp_block<K, PREC, MODE, FUSED, false, IRLS, false>(insts[lo], a, b - tile_start[lo]);
 }
 
 // A subset of the batch (a Compact list): a fixed grid strides over the
@@ -879,10 +882,10 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restric
     }
 }
 
-// Batch, between two Gauss-Newton launches: one block per registration
-// reduces the partials of the launch that just ran (if it processed the
-// registration), applies the update, and decides whether the next launch
-// processes the registration.  a.prev_level: level of that launch;
+// A batch subset, between two Gauss-Newton launches: one block per listed
+// registration reduces the partials of the launch that just ran (if it
+// processed the registration), applies the update, and decides whether the
+// next launch processes the registration.  a.prev_level: level of that launch;
 // a.first_of_level: the next launch starts a new level; a.check_max_iters: it
 // was the last launch of level 0.
 template <int PREC>
@@ -903,11 +906,6 @@ __device__ __forceinline__ void solve_block(const Inst &I, const StepArgs &a) {
         I.state[0] = S;
     }
     __syncthreads();  // S is reused when the caller loops
-}
-
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_solve_batch(const Inst *__restrict__ insts, StepArgs a) {
-    solve_block<PREC>(insts[blockIdx.x], a);
 }
 
 // The registrations of a Compact list only, a small grid striding over them.
