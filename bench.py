@@ -49,11 +49,11 @@ HBM_PEAK_GBS = 8000.0
 # device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.31, 1.0
-TRAFFIC_KIB = {"single": (2081.39, 58.17), "batch": (496609.39, 1075.96)}
-TRAFFIC_SRC_HASH = "c0348516e23afe6f"
-TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip", "ups_icp.hpp",
-               "ups_device.hpp", "ups_internal.hpp")
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.13, 1.0
+TRAFFIC_KIB = {"single": (2090.52, 58.17), "batch": (497076.89, 1142.68)}
+TRAFFIC_SRC_HASH = "f3f0f6cb8322bbf9"
+TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip",
+               "ups_icp_iter_batch_fused.hip", "ups_icp.hpp", "ups_device.hpp", "ups_internal.hpp")
 
 
 def traffic_bytes(which):
@@ -334,8 +334,9 @@ def run_batch(args, torch, ups, synth, W, stream):
     log(f"batch: {ms:.3f} ms per {N_BATCH} registrations, {N_BATCH / ms * 1e3:.0f} reg/s, "
         f"{ms / eq128 * 1e3:.2f} us per 128x1024-equivalent, {px_it / (ms * 1e-3) / 1e9:.1f} G px-it/s")
 
-    # dominant kernel: the batched level-0 Gauss-Newton launch, every
-    # registration active, timed alone with HIP events on its stream
+    # dominant kernel: the batched level-0 Gauss-Newton launch (the main
+    # loop's fused form), every registration active, timed alone with HIP
+    # events on its stream
     with torch.cuda.stream(stream):
         for _ in range(1 if args.profile_run else 2):
             batch.time_iteration(0, 5 if args.profile_run else 30)  # warm-up (clocks, caches), discarded
@@ -367,7 +368,8 @@ def run_batch(args, torch, ups, synth, W, stream):
         "autotune": tune,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_bytes("batch"),
-                     "kernel": f"k_icp_batch<{K[0]},{args.precision},iter> (level-0 launch over all {N_BATCH})",
+                     "kernel": f"k_icp_batch<{K[0]},{args.precision},iter,fused> (level-0 launch over all {N_BATCH}, "
+                               "the main loop's form, no update pending)",
                      "launch_us": round(launch_us, 2), "algorithmic_bytes_per_launch": alg_bytes},
     }
     if not args.no_proposal:

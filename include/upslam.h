@@ -434,7 +434,7 @@ ups_status ups_batch_grid_search(ups_context *ctx, ups_batch *b, const ups_grid_
 ups_status ups_autotune(ups_context *ctx, const char *cache_json_path);
 
 /* Time the batch's Gauss-Newton launch at pyramid level `level` alone: marks
- * every registration active at its current pose, enqueues n_launches
+ * every registration active at its current pose (no update pending), enqueues n_launches
  * back-to-back launches of that kernel between two HIP events on `stream`, and
  * returns their average duration in microseconds (synchronises the stream).
  * Leaves the registration states unusable for anything but a new

@@ -35,14 +35,17 @@ def _hipcc():
 HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
                  "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 SO_SANITIZED = os.path.join(HERE, "libupslam_san.so")
+# The same library with phase timestamps in the single-registration launches
+# (paper_2101_00585_amd.phase_split reads them); for profiling only.
+SO_PHASES = os.path.join(HERE, "libupslam_phases.so")
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False, phases: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
-    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build")
+    objdir = os.path.join(HERE, "_build_san" if sanitize else "_build_phases" if phases else "_build")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
-    flags = FLAGS + (HOST_SANITIZE if sanitize else [])
+    flags = FLAGS + (HOST_SANITIZE if sanitize else []) + (["-DUPS_PHASE_TIMESTAMPS"] if phases else [])
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
@@ -57,7 +60,7 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
-    so = SO_SANITIZED if sanitize else SO
+    so = SO_SANITIZED if sanitize else SO_PHASES if phases else SO
     tmp = so + ".tmp%d" % os.getpid()
     if sanitize:
         # the objects already hold their device code: a host link against the HIP runtime
@@ -73,4 +76,4 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv, phases="--phases" in sys.argv))

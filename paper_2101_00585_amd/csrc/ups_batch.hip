@@ -346,12 +346,14 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
     hipEvent_t e0, e1;
     UPS_CHECK_HIP(hipEventCreate(&e0));
     UPS_CHECK_HIP(hipEventCreate(&e1));
+    // the main loop's (fused) launch, state slot 0 in, no update pending: the
+    // same tile work every launch
     st = launch_icp_batch(b->K[level], b->p.precision, MODE_ITER, b->d_inst, b->d_tile_start + level * (b->n + 1),
-                          b->n, a, b->total_tiles[level], s);  // warm-up
+                          b->n, a, b->total_tiles[level], s, true);  // warm-up
     hipError_t e = hipEventRecord(e0, s);
     for (int k = 0; k < n_launches && st == UPS_OK && e == hipSuccess; k++)
         st = launch_icp_batch(b->K[level], b->p.precision, MODE_ITER, b->d_inst,
-                              b->d_tile_start + level * (b->n + 1), b->n, a, b->total_tiles[level], s);
+                              b->d_tile_start + level * (b->n + 1), b->n, a, b->total_tiles[level], s, true);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;

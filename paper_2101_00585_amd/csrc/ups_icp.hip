@@ -215,9 +215,17 @@ int pick_k_single(int npix) {
     return K;
 }
 
+// Every registration active at its current pose with no update pending (the
+// batch iteration launch timed alone).
 __global__ void k_activate_batch(const Inst *__restrict__ insts, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) insts[k].state[0].active = 1;
+    if (k >= n) return;
+    RegState &S = insts[k].state[0];
+    S.active = 1;
+    S.level_active = 1;
+    S.stop = 0;
+    S.pending = 0;
+    S.skip = 0;
 }
 
 ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s) {
@@ -298,6 +306,7 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
             a.parity = parity;
             a.first_of_level = it == 0;
             if ((st = launch_one(Ks[l], p.precision, MODE_ITER, I, a, I.nblocks[l], s)) != UPS_OK) return st;
+            a.seq++;
             a.init = nullptr;
             a.prev_level = l;
             parity ^= 1;

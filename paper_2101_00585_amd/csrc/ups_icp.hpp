@@ -53,6 +53,7 @@ struct StepArgs {
     int kpt;  // MODE_SCHED: pixels per thread of this tile (<= the kernel's K, a multiple of its pixel groups)
     const ups_pose *init;  // single registrations: the first launch builds the state from this start pose
     int reverse_tiles;  // debug: workgroups take the tiles in reverse order (set by the launchers)
+    int seq;            // single registrations: the launch's number within the call (phase timestamps)
 };
 
 // Debug tile order of the iteration / evaluation launches (ups_debug_reverse_tile_order).

@@ -1,6 +1,36 @@
 // Iteration / evaluation launches of a single registration, squared
 // objective, keyframe-frame arithmetic (the default path).
+#define UPS_PHASE_TU
 #include "ups_icp_kernels.hpp"
+
+#ifdef UPS_PHASE_TIMESTAMPS
+namespace ups {
+__device__ unsigned long long g_phase_mark[kPhaseLaunches][5];
+__device__ unsigned long long g_phase_first[kPhaseLaunches];
+__device__ unsigned long long g_phase_last[kPhaseLaunches];
+}  // namespace ups
+
+// Instrumented build only: copy the phase timestamps of the last calls to
+// out[64 * 7] (per launch: the five marks of tile 0, the earliest entry, the
+// latest exit), then reset them for the next call.
+extern "C" ups_status ups_debug_phase_read(unsigned long long *out) {
+    using namespace ups;
+    static unsigned long long h[kPhaseLaunches * 7];
+    unsigned long long *marks = h, *first = h + kPhaseLaunches * 5, *last = h + kPhaseLaunches * 6;
+    UPS_CHECK_HIP(hipMemcpyFromSymbol(marks, HIP_SYMBOL(g_phase_mark), sizeof(g_phase_mark)));
+    UPS_CHECK_HIP(hipMemcpyFromSymbol(first, HIP_SYMBOL(g_phase_first), sizeof(g_phase_first)));
+    UPS_CHECK_HIP(hipMemcpyFromSymbol(last, HIP_SYMBOL(g_phase_last), sizeof(g_phase_last)));
+    for (int i = 0; i < kPhaseLaunches * 7; i++) out[i] = h[i];
+    unsigned long long lo[kPhaseLaunches], hi[kPhaseLaunches];
+    for (int i = 0; i < kPhaseLaunches; i++) {
+        lo[i] = ~0ull;
+        hi[i] = 0;
+    }
+    UPS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_phase_first), lo, sizeof(lo)));
+    UPS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(g_phase_last), hi, sizeof(hi)));
+    return UPS_OK;
+}
+#endif
 
 namespace ups {
 

@@ -623,6 +623,38 @@ __device__ __forceinline__ void init_state(const Inst &I, const ups_pose *init, 
     S.level_active = 1;
 }
 
+// Phase timestamps of single-registration launches, in the instrumented build
+// only (UPS_PHASE_TIMESTAMPS, compiled into the translation unit that defines
+// UPS_PHASE_TU and the arrays): for launch a.seq of a call, the 100 MHz
+// real-time clock when tile 0's thread 0 enters, has the previous partials
+// reduced, has solved, has finished its pixels and has stored its partial,
+// plus the earliest entry and the latest exit over all blocks.
+#if defined(UPS_PHASE_TIMESTAMPS) && defined(UPS_PHASE_TU)
+constexpr int kPhaseLaunches = 64;
+extern __device__ unsigned long long g_phase_mark[kPhaseLaunches][5];
+extern __device__ unsigned long long g_phase_first[kPhaseLaunches];
+extern __device__ unsigned long long g_phase_last[kPhaseLaunches];
+#define UPS_PHASE(FUSED_, TILE_, SEQ_, K_)                                                                 \
+    do {                                                                                                 \
+        if ((FUSED_) && (TILE_) == 0 && threadIdx.x == 0 && (SEQ_) >= 0 && (SEQ_) < kPhaseLaunches)      \
+            g_phase_mark[SEQ_][K_] = __builtin_amdgcn_s_memrealtime();                                   \
+    } while (0)
+#define UPS_PHASE_FIRST(FUSED_, SEQ_)                                                                    \
+    do {                                                                                                 \
+        if ((FUSED_) && threadIdx.x == 0 && (SEQ_) >= 0 && (SEQ_) < kPhaseLaunches)                      \
+            atomicMin(&g_phase_first[SEQ_], __builtin_amdgcn_s_memrealtime());                          \
+    } while (0)
+#define UPS_PHASE_LAST(FUSED_, SEQ_)                                                                     \
+    do {                                                                                                 \
+        if ((FUSED_) && threadIdx.x == 0 && (SEQ_) >= 0 && (SEQ_) < kPhaseLaunches)                      \
+            atomicMax(&g_phase_last[SEQ_], __builtin_amdgcn_s_memrealtime());                            \
+    } while (0)
+#else
+#define UPS_PHASE(FUSED_, TILE_, SEQ_, K_) do {} while (0)
+#define UPS_PHASE_FIRST(FUSED_, SEQ_) do {} while (0)
+#define UPS_PHASE_LAST(FUSED_, SEQ_) do {} while (0)
+#endif
+
 // LDS workspace of one block's tile (one per kernel, whichever modes it runs).
 template <typename Acc>
 struct IcpShared {
@@ -644,6 +676,9 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     const double *part_in = I.partials + (size_t)a.parity * I.pstride * kPartialStride;
     double *part_out = I.partials + (size_t)(FUSED ? (a.parity ^ 1) : 0) * I.pstride * kPartialStride;
 
+    [[maybe_unused]] constexpr bool kPh = FUSED && STRIDED;  // phase timestamps: single registrations
+    UPS_PHASE_FIRST(kPh, a.seq);
+    UPS_PHASE(kPh, tile, a.seq, 0);
     RegState &S = sh.S;
     Acc(&qbuf)[31][65] = sh.qbuf;
     Acc(&tot)[32] = sh.tot;
@@ -705,6 +740,7 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         if (tid < kStateWords) ((uint32_t *)&S)[tid] = sword;
         if ((tid & 7) == 0 && (tid >> 3) < 29) tot[tid >> 3] = ptot;
         __syncthreads();
+        UPS_PHASE(kPh, tile, a.seq, 1);
         // ---- 0. the previous launch's update, solved identically by every block
         // (the first launch of a call: the state from the start pose)
         if (tid == 0) {
@@ -716,6 +752,7 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
             active = (MODE == MODE_EVAL) || (!S.stop && S.level_active);
         }
         __syncthreads();
+        UPS_PHASE(kPh, tile, a.seq, 2);
         if (!active) {
             if (tile == 0 && tid == 0) *slot_out = S;
             return;
@@ -808,6 +845,7 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         if (done) break;
     }
 
+    UPS_PHASE(kPh, tile, a.seq, 3);
     // ---- 2. block partial
     {
         Acc x[NV];
@@ -815,11 +853,13 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
         block_partial<NV, Acc, MODE == MODE_SCHED>(x, qbuf, part_out, I.pstride, tile, tot);
     }
+    UPS_PHASE(kPh, tile, a.seq, 4);
     if (FUSED && tile == 0 && tid == 0) {
         S.pending = (MODE == MODE_ITER);
         S.npartials = ntiles;
         *slot_out = S;
     }
+    UPS_PHASE_LAST(kPh, a.seq);
 }
 
 template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS, bool STRIDED = FUSED>
