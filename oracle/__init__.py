@@ -17,6 +17,11 @@ Each function follows a passage of the paper (arXiv 2101.00585):
 
 Where the paper gives no value or detail the reading is stated next to the
 function and in the defaults below.  Pins: tests/test_oracle_*.py.
+
+Parity unpinned: the exact weights of the a-trous filter (the paper names the
+filter but gives no taps, scales or number of levels).  Its invariants and
+its wide-sigma limit, a plain B3-spline convolution, are pinned; the weights
+themselves follow the stated reading only.
 """
 from __future__ import annotations
 

@@ -4,6 +4,9 @@
  * order, no blocking and no reordering beyond what each definition states.
  *
  * Parity pins for every function live in tests/test_oracle_*.py.
+ * Parity unpinned: the exact a-trous weights (orc_atrous; the paper gives no
+ * parameters) -- pinned only through the filter's invariants and its
+ * wide-sigma limit, a plain B3-spline convolution.
  */
 #include "orc.h"
 
