@@ -167,8 +167,8 @@ ups_status ups_context_create(ups_context **out, int device, int64_t max_pixels,
     if (e == hipSuccess) e = hipMalloc(&c->fill_key, max_pixels * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(c->fill_key, 0xFF, max_pixels * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&c->partials, 2 * c->max_partial_blocks * kPartialStride * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&c->state, 2 * sizeof(RegState));
-    if (e == hipSuccess) e = hipMemset(c->state, 0, 2 * sizeof(RegState));
+    if (e == hipSuccess) e = hipMalloc(&c->state, kSingleStateBytes);
+    if (e == hipSuccess) e = hipMemset(c->state, 0, kSingleStateBytes);
     if (e == hipSuccess) e = hipMalloc(&c->lut_arena, c->lut_capacity * sizeof(float2));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -259,6 +259,7 @@ static ups_status register_impl(ups_context *ctx, const ups_geom *scan_g, const 
         I.kf[l] = (const float4 *)kf_surfel_d;
     }
     I.state = ctx->state;
+    I.xsync = xsync_of(ctx->state);
     I.partials = ctx->partials;
     I.pstride = (int)ctx->max_partial_blocks;
     I.res = result_d;
@@ -401,6 +402,7 @@ ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const 
     I.scan[0] = (const float4 *)scan_surfel_d;
     I.kf[0] = (const float4 *)kf_surfel_d;
     I.state = ctx->state;
+    I.xsync = xsync_of(ctx->state);
     I.partials = ctx->partials;
     I.pstride = (int)ctx->max_partial_blocks;
     I.neq = out_d;

@@ -302,6 +302,20 @@ ups_status launch_register(const Inst &I0, const ups_pose *init, const ups_icp_p
     for (int l = p.levels - 1; l >= 0; l--) {
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
+        // a level small enough for one XCD runs all its iterations in one launch
+        // (the launches after it, at least the evaluation, zero its counters)
+        if (p.iters[l] >= 2 && I.xsync && I.nblocks[l] <= kLevelXcdMaxTiles && Ks[l] <= 2 &&
+            (a.irls_delta <= 0.f || (!I.world && p.precision == UPS_PREC_KAHAN_F64))) {
+            a.parity = parity;
+            a.first_of_level = 1;
+            if ((st = launch_icp_level_xcd(Ks[l], p.precision, I, a, p.iters[l], I.nblocks[l], s)) != UPS_OK)
+                return st;
+            a.seq += p.iters[l];
+            a.init = nullptr;
+            a.prev_level = l;
+            parity ^= p.iters[l] & 1;
+            continue;
+        }
         for (int it = 0; it < p.iters[l]; it++) {
             a.parity = parity;
             a.first_of_level = it == 0;

@@ -36,11 +36,23 @@ struct Inst {
     int nblocks[4];               // blocks (tiles) per level
     ups_icp_result *res;          // finish target (or null)
     ups_normal_eq *neq;           // finish target (or null)
+    unsigned int *xsync;          // single registrations: [4][2] ticket and arrival counters of the one-XCD level
+                                  // kernel per level (zero between calls; later launches reset them), or null
     // world-frame variant: the state pose is the scan's world pose, wR/wt the
     // keyframe's; init and result stay scan -> keyframe
     int world;
     double wR[9], wt[3];
 };
+
+// Scratch of a single registration (128-byte aligned): two state slots, then,
+// on a cache line of their own, the one-XCD level kernels' counters, a pair
+// per level (zero between calls).
+constexpr size_t kXsyncOffset = (2 * sizeof(RegState) + 127) / 128 * 128;
+constexpr size_t kSingleStateBytes = kXsyncOffset + 128;
+inline unsigned int *xsync_of(RegState *state) { return (unsigned int *)((char *)state + kXsyncOffset); }
+// Tiles of a level the one-XCD level kernel takes (they must all be resident
+// on one XCD's 32 CUs at once).
+constexpr int kLevelXcdMaxTiles = 32;
 
 // Per-launch arguments.
 struct StepArgs {
@@ -143,6 +155,11 @@ ups_status launch_icp_one_world(int K, int prec, int mode, const Inst &I, const 
                                 hipStream_t s);
 ups_status launch_icp_one_irls(int K, int prec, int mode, const Inst &I, const StepArgs &a, int blocks,
                                hipStream_t s);
+// All `iters` Gauss-Newton iterations of level a.level of a single
+// registration in one launch whose tiles all run on one XCD (see
+// k_icp_level_xcd); `tiles` = I.nblocks[a.level].
+ups_status launch_icp_level_xcd(int K, int prec, const Inst &I, const StepArgs &a, int iters, int tiles,
+                                hipStream_t s);
 ups_status launch_icp_batch_irls(int K, int prec, int mode, const Inst *insts, const int *tile_start, int n,
                                  const StepArgs &a, int blocks, hipStream_t s, bool fused);
 ups_status launch_icp_batch_list_irls(int K, int prec, int mode, const Inst *insts, const Compact *hdr,

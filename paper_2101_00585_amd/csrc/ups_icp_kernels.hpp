@@ -250,10 +250,13 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // of the group returns the same total, and every block that reads the same
 // partials computes the same totals.
 // NL: 16-byte loads in flight per thread (a chunk of 16 NL partials).
-template <int NV, typename Acc, int NL = 16>
+// COH: each pair as two agent-coherent 8-byte loads (partials that blocks of
+// the same launch wrote), the same sums.
+template <int NV, typename Acc, int NL = 16, bool COH = false>
 __device__ __forceinline__ Acc sum_partials(const double *part, int pstride, int n) {
     const int v = min((int)(threadIdx.x >> 3), NV - 1), g = threadIdx.x & 7;
     const UPS_AS_GLOBAL double *pv = (const UPS_AS_GLOBAL double *)part + (size_t)v * pstride;
+    const double *pc = part + (size_t)v * pstride;
     Acc t = 0;
     for (int b0 = 0; b0 < n; b0 += 16 * NL) {
         const int nk = min(NL, (n - b0 + 15) >> 4);  // block-uniform
@@ -262,7 +265,11 @@ __device__ __forceinline__ Acc sum_partials(const double *part, int pstride, int
         for (int k = 0; k < NL; k++) {
             // an index past the last partial is clamped into the row and its value unused
             x[k] = (v2d){0.0, 0.0};
-            if (k < nk) x[k] = *(const UPS_AS_GLOBAL v2d *)(pv + min(b0 + 16 * k + 2 * g, pstride - 2));
+            if (k < nk) {
+                const int b = min(b0 + 16 * k + 2 * g, pstride - 2);
+                if constexpr (COH) x[k] = (v2d){ld_coh_d(pc + b), ld_coh_d(pc + b + 1)};
+                else x[k] = *(const UPS_AS_GLOBAL v2d *)(pv + b);
+            }
         }
         Acc y[NL];
 #pragma unroll
@@ -603,6 +610,9 @@ __device__ __host__ __forceinline__ int npartials_of(int nblocks) { return nbloc
 // WORLD: the world-frame variant (state pose = the scan's world pose).
 // IRLS: the absolute-value objective of Equation 1, each inlier's terms
 // weighted by 1 / max(|r|, a.irls_delta).
+// COH (FUSED only): the state and the partials are read and written as
+// agent-coherent words, for blocks of one launch that hand them to each other
+// (the one-XCD level kernel); the same values as the plain accesses.
 // The state a registration starts from: the start pose (world-frame variant:
 // the scan's world pose, keyframe world pose x start pose, in FP64), status
 // CONVERGED, the first level active, no iterations run.
@@ -665,8 +675,9 @@ struct IcpShared {
     int job[8];  // persistent scheduler: ticket's registration and tile, last-arriver flag, spare, job (4 words)
 };
 
-template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS, bool STRIDED = FUSED>
+template <int K, int PREC, int MODE, bool FUSED, bool WORLD, bool IRLS, bool STRIDED = FUSED, bool COH = false>
 __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int tile, IcpShared<AccOf<PREC>> &sh) {
+    static_assert(!COH || (FUSED && MODE == MODE_ITER), "coherent hand-over: fused iterations only");
     constexpr int NV = (MODE == MODE_EVAL) ? 31 : 29;  // EVAL adds valid count and truncated cost
     using Acc = AccOf<PREC>;
     const int tid = threadIdx.x;
@@ -734,9 +745,10 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         // the state, one 32-bit word per thread, loaded alongside the partials
         static_assert(sizeof(RegState) % 4 == 0 && kStateWords <= kBlock, "state copy");
         uint32_t sword = 0;
-        if (tid < kStateWords) sword = ((const UPS_AS_GLOBAL uint32_t *)slot_in)[tid];
-        const Acc ptot =
-            sum_partials<29, Acc>(part_in, I.pstride, a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0);
+        if (tid < kStateWords)
+            sword = COH ? ld_coh((const uint32_t *)slot_in + tid) : ((const UPS_AS_GLOBAL uint32_t *)slot_in)[tid];
+        const Acc ptot = sum_partials<29, Acc, 16, COH>(part_in, I.pstride,
+                                                        a.prev_level >= 0 ? npartials_of(I.nblocks[a.prev_level]) : 0);
         if (tid < kStateWords) ((uint32_t *)&S)[tid] = sword;
         if ((tid & 7) == 0 && (tid >> 3) < 29) tot[tid >> 3] = ptot;
         __syncthreads();
@@ -851,13 +863,19 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         Acc x[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
-        block_partial<NV, Acc, MODE == MODE_SCHED>(x, qbuf, part_out, I.pstride, tile, tot);
+        block_partial<NV, Acc, MODE == MODE_SCHED || COH>(x, qbuf, part_out, I.pstride, tile, tot);
     }
     UPS_PHASE(kPh, tile, a.seq, 4);
-    if (FUSED && tile == 0 && tid == 0) {
-        S.pending = (MODE == MODE_ITER);
-        S.npartials = ntiles;
-        *slot_out = S;
+    if (FUSED && tile == 0) {
+        if (tid == 0) {
+            S.pending = (MODE == MODE_ITER);
+            S.npartials = ntiles;
+            if (!COH) *slot_out = S;
+        }
+        if constexpr (COH) {
+            __syncthreads();
+            state_st_coh(slot_out, S);
+        }
     }
     UPS_PHASE_LAST(kPh, a.seq);
 }
@@ -882,7 +900,95 @@ __device__ __forceinline__ int xcd_tile(int blk, int nblk, int reverse) {
 
 template <int K, int PREC, int MODE, bool WORLD, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
+    // the one-XCD level kernels' counters (a pair per level), zero again for
+    // the next call (those kernels, if they ran, ended before this launch)
+    if (blockIdx.x == 0 && threadIdx.x < 8 && I.xsync) I.xsync[threadIdx.x] = 0;
     icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles));
+}
+
+// Polls of a waiting block, at most, before it gives up (see k_icp_level_xcd).
+constexpr unsigned kLevelSpinLimit = 1u << 21;
+
+// All `iters` Gauss-Newton iterations of one pyramid level of a single
+// registration in one launch, its tiles on one XCD.  Workgroups are dealt to
+// the 8 XCDs in turn; a workgroup reads its XCD from the hardware and those
+// on XCD 0 take tickets (the tiles, in order) until the level's tiles are
+// taken; all others leave.  Between iterations the tiles hand their block
+// partials and the state to each other as agent-coherent words (a CU's L1
+// keeps lines across a workgroup-scope invalidate, so plain loads could
+// return what the same CU read an iteration earlier): every wavefront waits
+// for its stores, the workgroup counts itself in an atomic counter, polls it
+// (atomic adds of `zero`, never served from L1) until all tiles have arrived
+// and goes on with the next iteration, whose prologue reads the partials and
+// applies the update exactly as a separate launch would (the same sums,
+// bitwise the same result).  A level that converges or a registration
+// that stops ends the loop in every workgroup at once (they hold the same
+// state).  The last iteration's partials are left for the next launch; the
+// state goes to the slot that launch reads, (a.parity + iters) mod 2.  If a
+// workgroup waits longer than kLevelSpinLimit polls (the level's workgroups
+// could not all run on XCD 0 at once), the registration stops as DEGENERATE
+// rather than waiting on.  Each level has its own pair of counters; the
+// per-iteration and evaluation launches after this one zero them.
+template <int K, int PREC, bool WORLD, bool IRLS>
+__global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, int iters, unsigned zero) {
+    __shared__ IcpShared<AccOf<PREC>> sh;
+    __shared__ int ticket_s, fail_s;
+    const int tid = threadIdx.x;
+    const int ntiles = I.nblocks[a.level];
+    unsigned *const tickets = I.xsync + 2 * a.level, *const arrivals = tickets + 1;  // this level's pair
+    if (tid == 0) {
+        const unsigned xcd = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xFu;  // HW_REG_XCC_ID, bits 3:0
+        int t = -1;
+        if (xcd == 0) {
+            const unsigned k = __hip_atomic_fetch_add(tickets, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (k < (unsigned)ntiles) t = (int)k;
+        }
+        ticket_s = t;
+        fail_s = 0;
+    }
+    __syncthreads();
+    const int ticket = ticket_s;
+    if (ticket < 0) return;
+    const int tile = a.reverse_tiles ? ntiles - 1 - ticket : ticket;
+    unsigned spins = 0;
+    for (int it = 0; it < iters; it++) {
+        StepArgs ai = a;
+        ai.parity = (a.parity + it) & 1;
+        ai.seq = a.seq + it;
+        if (it > 0) {
+            ai.first_of_level = 0;
+            ai.prev_level = a.level;
+            ai.init = nullptr;
+        }
+        icp_tile<K, PREC, MODE_ITER, true, WORLD, IRLS, true, true>(I, ai, tile, sh);
+        if (!sh.active) break;  // converged or stopped: the same decision in every workgroup
+        if (it + 1 == iters) break;  // the last iteration's partials are the next launch's
+        // this workgroup's partial (and tile 0's state) stores completed, then its arrival
+        wait_stores();
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_fetch_add(arrivals, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned target = (unsigned)ntiles * (unsigned)(it + 1);
+            for (;;) {
+                const unsigned v = __hip_atomic_fetch_add(arrivals, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v >= target) break;
+                if (++spins > kLevelSpinLimit) {
+                    fail_s = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+        if (fail_s) break;
+    }
+    if (tid == 0 && fail_s) {
+        sh.S.stop = 1;
+        sh.S.pending = 0;
+        sh.S.status = UPS_DEGENERATE;
+    }
+    __syncthreads();
+    if (tile == 0 && tid == 0) I.state[(a.parity + iters) & 1] = sh.S;
 }
 
 // Batch: block -> (registration, tile) by binary search in the level's prefix

@@ -55,7 +55,7 @@ struct ups_context {
     unsigned long long *fill_key = nullptr;  // fuse fill pass, max_pixels
     double *partials = nullptr;              // [2][kPartialStride][max_partial_blocks] block partials
     int64_t max_partial_blocks = 0;
-    ups::RegState *state = nullptr;          // [2] registration state slots
+    ups::RegState *state = nullptr;          // [2] registration state slots, then two counters (kSingleStateBytes)
     // ray tables
     float2 *lut_arena = nullptr;
     size_t lut_capacity = 0, lut_used = 0;  // in float2

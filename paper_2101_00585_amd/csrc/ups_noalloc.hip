@@ -1,8 +1,9 @@
 // ups_register_scan_noalloc: the registration of ups_register_scan (Section
 // III-B) for callers that cannot allocate device memory.  No context: the
 // scratch the registration kernels need beyond their inputs and outputs --
-// both panoramas' ray tables, the block partials and the two state slots --
-// lives in one static device array per GPU, `scratch`, of kScratchBytes.  Host code never passes the array's name
+// both panoramas' ray tables, the block partials, the two state slots and the
+// one-XCD level kernels' counters -- lives in one static device array per
+// GPU, `scratch`, of kScratchBytes.  Host code never passes the array's name
 // to a kernel (on the host it is only a stand-in for the symbol): the device
 // address of each GPU's copy is looked up once per device with
 // hipGetSymbolAddress and kept in g_scratch[device].
@@ -10,7 +11,9 @@
 // Every call on a GPU uses that GPU's copy and leaves its contents behind.
 // Each call writes the ray tables and the registration state before any
 // kernel reads them, and a launch reads only block partials an earlier
-// launch of the same call wrote, so nothing has to start at zero.  Calls that
+// launch of the same call wrote.  The level counters must be zero when a call
+// starts: they are zero when the code object is loaded (static storage), and
+// every call's launches after the level kernel zero them again.  Calls that
 // overlap in time on one GPU (two streams, two threads) race on the array.
 #include <cmath>
 #include <mutex>
@@ -33,7 +36,7 @@ constexpr int64_t kPstride = (kMaxPixels / kBlock + 64 + 15) / 16 * 16;
 constexpr int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 constexpr int64_t kLutBytes = align256(kMaxLut * (int64_t)sizeof(float2));
 constexpr int64_t kPartialBytes = align256(2 * kPartialStride * kPstride * (int64_t)sizeof(double));
-constexpr int64_t kStateBytes = align256(2 * (int64_t)sizeof(RegState));
+constexpr int64_t kStateBytes = align256((int64_t)kSingleStateBytes);
 
 // byte offsets of the sections
 constexpr int64_t kOffLutScan = 0;
@@ -142,6 +145,7 @@ extern "C" ups_status ups_register_scan_noalloc(const ups_geom *scan_g, const fl
         I.kf[l] = (const float4 *)kf_surfel_d;
     }
     I.state = (RegState *)(base + kOffState);
+    I.xsync = xsync_of(I.state);
     I.partials = (double *)(base + kOffPartials);
     I.pstride = (int)kPstride;
     I.res = result_d;
