@@ -4,9 +4,12 @@ Loads the instrumented library (`python -m paper_2101_00585_amd.build
 --phases` writes libupslam_phases.so: the same kernels plus real-time clock
 marks), registers the 128x1024 outdoor scan against its keyframe fused from
 ten scans (3 levels, 10 iterations each) from a HIP graph, and prints for
-every Gauss-Newton launch and the evaluation launch, in microseconds (100 MHz
-clock, mean over `reps` replays):
-  gap       the previous launch's last block exit to this launch's first entry
+every Gauss-Newton iteration and the evaluation launch, in microseconds (100
+MHz clock, mean over `reps` replays); the iterations of a level that runs in
+one launch (the one-XCD level kernel) are timed like separate launches:
+  gap       the previous iteration's last block exit to this one's first
+            entry (a launch gap, or the level kernel's exchange between
+            iterations)
   partials  tile 0: entry to the previous launch's partials and state reduced
   solve     tile 0: the FP64 solve and pose update (thread 0)
   pixels    tile 0: its pixels (association, terms, per-thread sums)
