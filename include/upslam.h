@@ -182,6 +182,16 @@ const char *ups_last_error(void);
  * order they were enqueued with.  Always UPS_OK. */
 ups_status ups_debug_reverse_tile_order(int32_t reversed);
 
+/* Debug (failure handling of the one-XCD level kernel, which runs all
+ * Gauss-Newton iterations of a coarse pyramid level of a single registration,
+ * Section III-B, in one launch whose workgroups wait for each other between
+ * iterations): a waiting workgroup of a level kernel enqueued afterwards gives
+ * up after `polls` unsuccessful polls in all (0: at its first) and the
+ * registration ends as UPS_DEGENERATE; the launch still ends.  polls < 0
+ * restores the default, 2^21.  Process-wide; launches already enqueued or
+ * captured keep their limit.  UPS_ERR_INVALID_ARG if polls >= 2^32. */
+ups_status ups_debug_level_spin_limit(int64_t polls);
+
 /* Surfel image (Section III-A) from a range image.  depth_d: float[rows][cols];
  * surfel_d: float[rows][cols][4] output (must not alias depth_d). */
 ups_status ups_panorama_normals(ups_context *ctx, const ups_geom *g, const float *depth_d, float *surfel_d,

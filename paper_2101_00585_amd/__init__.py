@@ -123,6 +123,7 @@ def load():
         "ups_batch_schedule": [_P, _P, _P],
         "ups_batch_set_scheduler": [_P, ctypes.c_int32],
         "ups_debug_reverse_tile_order": [ctypes.c_int32],
+        "ups_debug_level_spin_limit": [ctypes.c_int64],
         "ups_splat_sweep": [_P, _P, _P, _P, _P, _P, _P],
         "ups_keyframe_consistency": [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P],
         "ups_classify_loop_closures": [_P, ctypes.c_int32, _P, ctypes.c_double, _P, _P, _P],
@@ -567,6 +568,13 @@ def debug_reverse_tile_order(reversed_: bool):
     """Debug: later registration launches deal their tiles to workgroups in
     reverse order (results must not change)."""
     _check(_LIB.ups_debug_reverse_tile_order(1 if reversed_ else 0))
+
+
+def debug_level_spin_limit(polls: int):
+    """Debug: a waiting workgroup of a later one-XCD level kernel gives up
+    after `polls` unsuccessful polls (0: at its first) and the registration
+    ends as DEGENERATE; a negative value restores the default limit."""
+    _check(_LIB.ups_debug_level_spin_limit(int(polls)))
 
 
 # ----------------------------------------------------------------------------

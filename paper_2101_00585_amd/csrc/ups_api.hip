@@ -11,6 +11,7 @@ namespace ups {
 
 static thread_local std::string g_last_error;
 static std::atomic<int> g_reverse_tiles{0};
+static std::atomic<unsigned> g_level_spin_limit{ups::kLevelSpinLimit};
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
@@ -132,6 +133,7 @@ using namespace ups;
 
 namespace ups {
 bool debug_reverse_tiles() { return g_reverse_tiles.load(std::memory_order_relaxed) != 0; }
+unsigned level_spin_limit() { return g_level_spin_limit.load(std::memory_order_relaxed); }
 }  // namespace ups
 
 extern "C" {
@@ -140,6 +142,12 @@ const char *ups_last_error(void) { return g_last_error.c_str(); }
 
 ups_status ups_debug_reverse_tile_order(int32_t reversed) {
     g_reverse_tiles.store(reversed ? 1 : 0, std::memory_order_relaxed);
+    return UPS_OK;
+}
+
+ups_status ups_debug_level_spin_limit(int64_t polls) {
+    UPS_REQUIRE(polls < ((int64_t)1 << 32), "polls must be below 2^32");
+    g_level_spin_limit.store(polls < 0 ? kLevelSpinLimit : (unsigned)polls, std::memory_order_relaxed);
     return UPS_OK;
 }
 

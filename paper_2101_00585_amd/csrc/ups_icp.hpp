@@ -53,6 +53,11 @@ inline unsigned int *xsync_of(RegState *state) { return (unsigned int *)((char *
 // Tiles of a level the one-XCD level kernel takes (they must all be resident
 // on one XCD's 32 CUs at once).
 constexpr int kLevelXcdMaxTiles = 32;
+// Unsuccessful polls of a waiting workgroup of the level kernel, in all, after
+// which it gives up and the registration ends as DEGENERATE; the setting of
+// later launches (ups_debug_level_spin_limit).
+constexpr unsigned kLevelSpinLimit = 1u << 21;
+unsigned level_spin_limit();
 
 // Per-launch arguments.
 struct StepArgs {

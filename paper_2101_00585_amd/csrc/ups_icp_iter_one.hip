@@ -57,15 +57,17 @@ ups_status launch_icp_one_plain(int K, int prec, int mode, const Inst &I, const 
 template <int K, int PREC>
 static void launch_level_t(const Inst &I, const StepArgs &a0, int iters, int blocks, hipStream_t s) {
     const StepArgs a = with_tile_order(a0);
+    const unsigned spin = level_spin_limit();
     if (I.world)
-        hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, true, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters, 0u);
+        hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, true, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters, 0u,
+                           spin);
     else if (a.irls_delta > 0.f) {
         if constexpr (PREC == UPS_PREC_KAHAN_F64)
             hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, false, true>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters,
-                               0u);
+                               0u, spin);
     } else
         hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, false, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters,
-                           0u);
+                           0u, spin);
 }
 
 ups_status launch_icp_level_xcd(int K, int prec, const Inst &I, const StepArgs &a, int iters, int tiles,

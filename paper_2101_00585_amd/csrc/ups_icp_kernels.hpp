@@ -906,9 +906,6 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
     icp_block<K, PREC, MODE, true, WORLD, IRLS>(I, a, xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles));
 }
 
-// Polls of a waiting block, at most, before it gives up (see k_icp_level_xcd).
-constexpr unsigned kLevelSpinLimit = 1u << 21;
-
 // All `iters` Gauss-Newton iterations of one pyramid level of a single
 // registration in one launch, its tiles on one XCD.  Workgroups are dealt to
 // the 8 XCDs in turn; a workgroup reads its XCD from the hardware and those
@@ -924,13 +921,21 @@ constexpr unsigned kLevelSpinLimit = 1u << 21;
 // bitwise the same result).  A level that converges or a registration
 // that stops ends the loop in every workgroup at once (they hold the same
 // state).  The last iteration's partials are left for the next launch; the
-// state goes to the slot that launch reads, (a.parity + iters) mod 2.  If a
-// workgroup waits longer than kLevelSpinLimit polls (the level's workgroups
-// could not all run on XCD 0 at once), the registration stops as DEGENERATE
-// rather than waiting on.  Each level has its own pair of counters; the
+// state goes to the slot that launch reads, (a.parity + iters) mod 2.  A
+// workgroup whose unsuccessful polls exceed spin_limit in all (the level's
+// workgroups could not all run on XCD 0 at once) gives up rather than waiting
+// on: it sets the counter's top bit, so every other workgroup gives up at its
+// next poll and the launch ends, and it overwrites its partial of the level's
+// last iteration with NaN, which the launch that reads it turns into the
+// DEGENERATE status (its solve finds no positive pivot).  Tile 0 giving up
+// stores the DEGENERATE state itself; either way the registration never goes
+// on from a sum that lacks a tile.  Each level has its own pair of counters; the
 // per-iteration and evaluation launches after this one zero them.
+constexpr unsigned kLevelGaveUp = 1u << 31;  // arrival counter bit: a workgroup gave up
+
 template <int K, int PREC, bool WORLD, bool IRLS>
-__global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, int iters, unsigned zero) {
+__global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, int iters, unsigned zero,
+                                                          unsigned spin_limit) {
     __shared__ IcpShared<AccOf<PREC>> sh;
     __shared__ int ticket_s, fail_s;
     const int tid = threadIdx.x;
@@ -971,9 +976,14 @@ __global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, in
             const unsigned target = (unsigned)ntiles * (unsigned)(it + 1);
             for (;;) {
                 const unsigned v = __hip_atomic_fetch_add(arrivals, zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (v >= target) break;
-                if (++spins > kLevelSpinLimit) {
+                if (v & kLevelGaveUp) {  // another workgroup gave up: so does this one
                     fail_s = 1;
+                    break;
+                }
+                if (v >= target) break;
+                if (++spins > spin_limit) {
+                    fail_s = 1;
+                    __hip_atomic_fetch_or(arrivals, kLevelGaveUp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -982,10 +992,15 @@ __global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, in
         __syncthreads();
         if (fail_s) break;
     }
-    if (tid == 0 && fail_s) {
-        sh.S.stop = 1;
-        sh.S.pending = 0;
-        sh.S.status = UPS_DEGENERATE;
+    if (fail_s) {
+        double *last = I.partials + (size_t)((a.parity + iters) & 1) * I.pstride * kPartialStride;
+        if (tid < kPartialStride)
+            st_coh_d(last + (size_t)tid * I.pstride + tile, __longlong_as_double(0x7ff8000000000000ll));
+        if (tid == 0) {
+            sh.S.stop = 1;
+            sh.S.pending = 0;
+            sh.S.status = UPS_DEGENERATE;
+        }
     }
     __syncthreads();
     if (tile == 0 && tid == 0) I.state[(a.parity + iters) & 1] = sh.S;

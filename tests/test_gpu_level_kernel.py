@@ -1,0 +1,71 @@
+"""Failure handling of the one-XCD level kernel (the Gauss-Newton iterations
+of Section III-B for a coarse level of a single registration in one launch,
+its workgroups waiting for each other between iterations), forced from the
+host: with a limit of zero unsuccessful polls, a workgroup that finds the
+others not yet arrived gives up, every other one gives up at its next poll,
+and the registration ends as DEGENERATE instead of going on from a sum that
+lacks a tile.  Every kernel still exits normally.  The next call with the
+default limit must give bitwise the result of a call before the failure (the
+counters and partials the failed call left behind are not read)."""
+import numpy as np
+import pytest
+
+import synth
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu_lib):
+    c = gpu_lib.Context(0, max_pixels=128 * 1024)
+    yield c
+    c.close()
+
+
+@pytest.fixture
+def spin_limit(gpu_lib):
+    """Set the level kernel's poll limit for the test, restore the default afterwards."""
+    yield gpu_lib.debug_level_spin_limit
+    gpu_lib.debug_level_spin_limit(-1)
+
+
+@pytest.mark.parametrize("size", [(128, 1024), (64, 512)], ids=["128x1024", "64x512"])
+def test_level_kernel_give_up_ends_degenerate(gpu_lib, ctx, spin_limit, size):
+    import torch
+    c = W.config0(rows=size[0], cols=size[1])
+    g = c["geom"]
+    kf = gpu_lib.panorama_normals(ctx, g, _t(c["kf"].astype(np.float32)))
+    scan = gpu_lib.panorama_normals(ctx, g, _t(c["scan"].astype(np.float32)))
+    p = gpu_lib.IcpParams(levels=3, iters=(10, 10, 10))
+    init = synth.se3(synth.rot_z(0.02), [0.1, -0.05, 0.0])
+    print(f"\n{size}: reference call", flush=True)
+    ref = gpu_lib.register_scan(ctx, g, scan, g, kf, init, p)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy().copy()
+    r0 = gpu_lib.read_result(torch.from_numpy(ref))
+    assert r0["status"] == gpu_lib.STATUS_CONVERGED and r0["iters_run"] == 30
+    print("zero-poll limit", flush=True)
+    spin_limit(0)
+    bad = gpu_lib.register_scan(ctx, g, scan, g, kf, init, p)
+    torch.cuda.synchronize()
+    rb = gpu_lib.read_result(bad)
+    print(f"gave up: status {rb['status']}, iterations {rb['iters_run']}, per level {rb['level_iters']}")
+    assert rb["status"] == gpu_lib.STATUS_DEGENERATE
+    # a coarse level gave up: no update at level 0 (it never runs in one launch)
+    assert rb["iters_run"] < 30 and rb["level_iters"][0] == 0
+    print("default limit again", flush=True)
+    spin_limit(-1)
+    again = gpu_lib.register_scan(ctx, g, scan, g, kf, init, p)
+    torch.cuda.synchronize()
+    assert np.array_equal(again.cpu().numpy(), ref)
+
+
+def test_level_spin_limit_rejects_out_of_range(gpu_lib):
+    with pytest.raises(Exception):
+        gpu_lib.debug_level_spin_limit(1 << 32)
