@@ -5,6 +5,8 @@
 // default precision mode).  Both are in the translation unit that holds the
 // phase timestamps of the instrumented build.
 #define UPS_PHASE_TU
+#include <atomic>
+
 #include "ups_icp_kernels.hpp"
 
 #ifdef UPS_PHASE_TIMESTAMPS
@@ -54,20 +56,25 @@ ups_status launch_icp_one_plain(int K, int prec, int mode, const Inst &I, const 
     return UPS_OK;
 }
 
+// The XCD whose workgroups take the tiles, rotated over the 8 from launch to
+// launch (process-wide).
+static std::atomic<unsigned> g_level_xcd{0};
+
 template <int K, int PREC>
 static void launch_level_t(const Inst &I, const StepArgs &a0, int iters, int blocks, hipStream_t s) {
     const StepArgs a = with_tile_order(a0);
     const unsigned spin = level_spin_limit();
+    const unsigned xcd = g_level_xcd.fetch_add(1, std::memory_order_relaxed) & 7u;
     if (I.world)
-        hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, true, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters, 0u,
-                           spin);
+        hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, true, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters, xcd,
+                           0u, spin);
     else if (a.irls_delta > 0.f) {
         if constexpr (PREC == UPS_PREC_KAHAN_F64)
             hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, false, true>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters,
-                               0u, spin);
+                               xcd, 0u, spin);
     } else
         hipLaunchKernelGGL((k_icp_level_xcd<K, PREC, false, false>), dim3(blocks), dim3(kBlock), 0, s, I, a, iters,
-                           0u, spin);
+                           xcd, 0u, spin);
 }
 
 ups_status launch_icp_level_xcd(int K, int prec, const Inst &I, const StepArgs &a, int iters, int tiles,
@@ -76,7 +83,7 @@ ups_status launch_icp_level_xcd(int K, int prec, const Inst &I, const StepArgs &
         set_error("no one-XCD level kernel for this registration");
         return UPS_ERR_INVALID_ARG;
     }
-    // eight workgroups per tile: the XCD that takes the tiles receives one per tile
+    // eight workgroups per tile: each XCD, the one that takes the tiles among them, receives one per tile
     const int blocks = 8 * tiles;
     switch (K) {
         case 1: UPS_DISPATCH_P(prec, (launch_level_t<1, PP>(I, a, iters, blocks, s))) break;

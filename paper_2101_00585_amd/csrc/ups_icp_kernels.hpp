@@ -909,8 +909,10 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 // All `iters` Gauss-Newton iterations of one pyramid level of a single
 // registration in one launch, its tiles on one XCD.  Workgroups are dealt to
 // the 8 XCDs in turn; a workgroup reads its XCD from the hardware and those
-// on XCD 0 take tickets (the tiles, in order) until the level's tiles are
-// taken; all others leave.  Between iterations the tiles hand their block
+// on XCD `xcd_sel` take tickets (the tiles, in order) until the level's tiles
+// are taken; all others leave.  The host rotates xcd_sel from launch to
+// launch, so that level kernels running at once on several streams wait on
+// different XCDs (each XCD holds the workgroups of two of them at a time).  Between iterations the tiles hand their block
 // partials and the state to each other as agent-coherent words (a CU's L1
 // keeps lines across a workgroup-scope invalidate, so plain loads could
 // return what the same CU read an iteration earlier): every wavefront waits
@@ -934,8 +936,8 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 constexpr unsigned kLevelGaveUp = 1u << 31;  // arrival counter bit: a workgroup gave up
 
 template <int K, int PREC, bool WORLD, bool IRLS>
-__global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, int iters, unsigned zero,
-                                                          unsigned spin_limit) {
+__global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, int iters, unsigned xcd_sel,
+                                                          unsigned zero, unsigned spin_limit) {
     __shared__ IcpShared<AccOf<PREC>> sh;
     __shared__ int ticket_s, fail_s;
     const int tid = threadIdx.x;
@@ -944,7 +946,7 @@ __global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, in
     if (tid == 0) {
         const unsigned xcd = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xFu;  // HW_REG_XCC_ID, bits 3:0
         int t = -1;
-        if (xcd == 0) {
+        if (xcd == xcd_sel) {
             const unsigned k = __hip_atomic_fetch_add(tickets, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (k < (unsigned)ntiles) t = (int)k;
         }

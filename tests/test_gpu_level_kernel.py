@@ -69,3 +69,53 @@ def test_level_kernel_give_up_ends_degenerate(gpu_lib, ctx, spin_limit, size):
 def test_level_spin_limit_rejects_out_of_range(gpu_lib):
     with pytest.raises(Exception):
         gpu_lib.debug_level_spin_limit(1 << 32)
+
+
+def test_level_kernels_on_concurrent_streams(gpu_lib):
+    """Four registrations, each in its own context, replayed from graphs on
+    four streams at once: their one-XCD level kernels run concurrently (on
+    different XCDs: the host rotates the XCD that takes the tiles), and each
+    result is bitwise the sequential one, three replays in a row."""
+    import torch
+    n = 4
+    ctxs = [gpu_lib.Context(0, max_pixels=128 * 1024) for _ in range(n)]
+    try:
+        c = W.config0(rows=128, cols=1024)
+        g = c["geom"]
+        kf = gpu_lib.panorama_normals(ctxs[0], g, _t(c["kf"].astype(np.float32)))
+        scan = gpu_lib.panorama_normals(ctxs[0], g, _t(c["scan"].astype(np.float32)))
+        p = gpu_lib.IcpParams(levels=3, iters=(10, 10, 10))
+        init = synth.se3(synth.rot_z(0.02), [0.1, -0.05, 0.0])
+        ref = gpu_lib.register_scan(ctxs[0], g, scan, g, kf, init, p)
+        torch.cuda.synchronize()
+        ref = ref.cpu().numpy().copy()
+        dev = torch.device("cuda:0")
+        streams = [torch.cuda.Stream() for _ in range(n)]
+        graphs, results, inits = [], [], []
+        for k in range(n):
+            res = gpu_lib.new_result(dev)
+            init_d = gpu_lib.pose_tensor(init, dev)
+            with torch.cuda.stream(streams[k]):
+                gpu_lib.register_scan(ctxs[k], g, scan, g, kf, init_d, p, res)
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=streams[k]):
+                gpu_lib.register_scan(ctxs[k], g, scan, g, kf, init_d, p, res)
+            graphs.append(gr)
+            results.append(res)
+            inits.append(init_d)
+        for rep in range(3):
+            for r in results:
+                r.zero_()
+            torch.cuda.synchronize()
+            print(f"replay {rep}", flush=True)
+            for k in range(n):
+                with torch.cuda.stream(streams[k]):
+                    graphs[k].replay()
+            torch.cuda.synchronize()
+            for k in range(n):
+                assert np.array_equal(results[k].cpu().numpy(), ref), (rep, k)
+    finally:
+        torch.cuda.synchronize()
+        for cx in ctxs:
+            cx.close()
