@@ -925,7 +925,7 @@ __global__ __launch_bounds__(kBlock) void k_icp_one(Inst I, StepArgs a) {
 // state).  The last iteration's partials are left for the next launch; the
 // state goes to the slot that launch reads, (a.parity + iters) mod 2.  A
 // workgroup whose unsuccessful polls exceed spin_limit in all (the level's
-// workgroups could not all run on XCD 0 at once) gives up rather than waiting
+// workgroups could not all run on the chosen XCD at once) gives up rather than waiting
 // on: it sets the counter's top bit, so every other workgroup gives up at its
 // next poll and the launch ends, and it overwrites its partial of the level's
 // last iteration with NaN, which the launch that reads it turns into the
