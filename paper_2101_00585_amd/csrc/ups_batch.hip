@@ -6,8 +6,9 @@
 // scheduler's ticket map.  A call (ups_register_batch) starts with one prepare
 // launch (states and pyramids of all registrations), then runs the
 // Gauss-Newton iterations under one of two schedulers:
-//   launches: per iteration one launch over every tile of the level (blocks of
-//     registrations that stopped exit at once) and one solve launch;
+//   launches: per iteration one launch over every tile of the level, each
+//     block first applying its registration's pending update (blocks of
+//     registrations that stopped exit at once);
 //   persistent: the scheduler's set-up (the first job of every registration)
 //     and one persistent launch in which every registration advances through
 //     its iterations independently of the others (k_icp_persistent; a
@@ -48,7 +49,16 @@ struct ups_batch {
     ups_icp_result *alt = nullptr;   // [n] fallback results
     Compact *comp = nullptr;         // the registrations the fallback reruns ...
     int *comp_list = nullptr;        // ... [n]
-    int *comp_start = nullptr;       // ... and their tile prefix tables [4][n+1]
+    int *comp_start = nullptr;       // ... and their tile prefix tables [4][n+1] (subset tiles)
+    // the fallback's launches over a subset tile each level with as few pixels
+    // per thread as keep every registration within 256 tiles (a subset is
+    // small: more, shorter tiles), with descriptors and partial buffers of
+    // their own (the states are the batch's)
+    int Ks[4] = {1, 1, 1, 1};
+    int total_tiles_sub[4] = {0, 0, 0, 0};
+    Inst *d_inst_sub = nullptr;        // [n]
+    int *d_tile_start_sub = nullptr;   // [4][n+1]
+    double *partials_sub = nullptr;    // [n][2][kPartialStride][pstride of the subset tiles]
     int scheduler = UPS_SCHED_LAUNCHES;
     // persistent scheduler
     int Kp = 0;                       // the persistent kernel's pixels per thread (the largest of kpt)
@@ -62,8 +72,9 @@ struct ups_batch {
 };
 
 // Grid of the launches over a subset of the batch (the fallback): they stride
-// over the subset's tiles, so that they cost little when it is small.
-constexpr int kListBlocks = 512, kListSolveBlocks = 32;
+// over the subset's tiles (its registrations, for the results), so that they
+// cost little when it is small.
+constexpr int kListBlocks = 512, kListFinishBlocks = 32;
 
 namespace {
 
@@ -82,6 +93,9 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->mask);
     (void)hipFree(b->alt);
     (void)hipFree(b->comp);
+    (void)hipFree(b->d_inst_sub);
+    (void)hipFree(b->d_tile_start_sub);
+    (void)hipFree(b->partials_sub);
     (void)hipFree(b->sched);
     (void)hipFree(b->tile_map);
     (void)hipFree(b->jobs);
@@ -147,6 +161,11 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         }
         b->K[l] = K;
     }
+    for (int l = 0; l < L; l++) {
+        int K = 1;
+        while (K < b->K[l] && ((max_npix >> (2 * l)) + kBlock * K - 1) / (kBlock * K) > 256) K *= 2;
+        b->Ks[l] = K;
+    }
     // the persistent kernel is compiled for the largest of these and tiles
     // each level with its own (at least a pixel group of the kernel, 4), so
     // no level has more tiles than the partial buffers hold
@@ -161,9 +180,10 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
 
     // host descriptors
     std::vector<Inst> hi(n);
-    std::vector<int> tile_start(4 * (n + 1), 0), pre_start(n + 1, 0);
+    std::vector<int> tile_start(4 * (n + 1), 0), tile_start_sub(4 * (n + 1), 0), pre_start(n + 1, 0);
+    std::vector<int> nblocks_sub(4 * (size_t)n, 0);
     int64_t pyr_total = 0;
-    int pstride = 1;
+    int pstride = 1, pstride_sub = 1;
     std::vector<int64_t> pyr_off_s(n), pyr_off_k(n);
     for (int k = 0; k < n; k++) {
         const ups_batch_item &it = items[k];
@@ -180,6 +200,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
             const int np = I.sg[l].rows * I.sg[l].cols;
             I.nblocks[l] = (np + kBlock * b->K[l] - 1) / (kBlock * b->K[l]);
             pstride = std::max(pstride, I.nblocks[l]);
+            nblocks_sub[4 * k + l] = (np + kBlock * b->Ks[l] - 1) / (kBlock * b->Ks[l]);
+            pstride_sub = std::max(pstride_sub, nblocks_sub[4 * k + l]);
             if (l == 1) pre += np + I.kg[l].rows * I.kg[l].cols;
         }
         pyr_off_s[k] = pyr_total;
@@ -192,6 +214,9 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         for (int k = 0; k < n; k++)
             tile_start[l * (n + 1) + k + 1] = tile_start[l * (n + 1) + k] + (l < L ? hi[k].nblocks[l] : 0);
         b->total_tiles[l] = tile_start[l * (n + 1) + n];
+        for (int k = 0; k < n; k++)
+            tile_start_sub[l * (n + 1) + k + 1] = tile_start_sub[l * (n + 1) + k] + nblocks_sub[4 * k + l];
+        b->total_tiles_sub[l] = tile_start_sub[l * (n + 1) + n];
     }
     b->total_pre = pre_start[n];
     // tickets of a call, at most: every iteration of every level of every
@@ -244,6 +269,10 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->mask, (size_t)n);
     alloc((void **)&b->alt, (size_t)n * sizeof(ups_icp_result));
     alloc((void **)&b->comp, sizeof(Compact) + ((size_t)n + 4 * ((size_t)n + 1)) * sizeof(int) + 64);
+    alloc((void **)&b->d_inst_sub, n * sizeof(Inst));
+    alloc((void **)&b->d_tile_start_sub, tile_start_sub.size() * sizeof(int));
+    pstride_sub = (int)partial_stride(pstride_sub);
+    alloc((void **)&b->partials_sub, (size_t)n * 2 * pstride_sub * kPartialStride * sizeof(double));
     alloc((void **)&b->sched, sizeof(Sched));
     alloc((void **)&b->tile_map, (size_t)b->map_size * sizeof(unsigned long long));
     alloc((void **)&b->jobs, (size_t)n * sizeof(SchedJob));
@@ -296,6 +325,18 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         alloc((void **)&b->d_ntile_start, ntile_start.size() * sizeof(int));
     }
     if (e == hipSuccess) e = hipMemcpy(b->d_inst, hi.data(), n * sizeof(Inst), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        std::vector<Inst> hs(hi);
+        for (int k = 0; k < n; k++) {
+            for (int l = 0; l < 4; l++) hs[k].nblocks[l] = nblocks_sub[4 * k + l];
+            hs[k].partials = b->partials_sub + (size_t)k * 2 * pstride_sub * kPartialStride;
+            hs[k].pstride = pstride_sub;
+        }
+        e = hipMemcpy(b->d_inst_sub, hs.data(), n * sizeof(Inst), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_tile_start_sub, tile_start_sub.data(), tile_start_sub.size() * sizeof(int),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -447,8 +488,10 @@ ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_re
 
 // A call over the masked-in registrations (the fallback): their pyramids left
 // by the previous call are reused, and the launches go through the batch's
-// Compact list of them, with one solve launch per iteration (pose in state
-// slot 0).
+// Compact list of them, tiled with the subset's pixels per thread (Ks), in the
+// main loop's fused form: prepare, one launch per Gauss-Newton iteration in
+// which each tile first applies its registration's pending update, the
+// evaluation launch, and the results of the listed registrations.
 ups_status register_batch_subset(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
                                  hipStream_t s) {
     ups_status st;
@@ -463,33 +506,32 @@ ups_status register_batch_subset(ups_batch *b, const ups_pose *init_d, const uin
     a.min_inliers = p.min_inliers;
     a.stop_norm = p.stop_update_norm;
     a.prev_level = -1;
-    // (level, iteration) sequence of the Gauss-Newton launches
-    std::vector<int> seq;
-    for (int l = p.levels - 1; l >= 0; l--)
-        for (int it = 0; it < p.iters[l]; it++) seq.push_back(l);
-    for (size_t q = 0; q < seq.size(); q++) {
-        const int l = seq[q];
+    int parity = 0;
+    for (int l = p.levels - 1; l >= 0; l--) {
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
-        if ((st = launch_icp_batch_list(b->K[l], p.precision, MODE_ITER, b->d_inst, b->comp, b->comp_list,
-                                        b->comp_start + l * (n + 1), n, a, std::min(b->total_tiles[l], kListBlocks),
-                                        s)) != UPS_OK)
-            return st;
-        StepArgs sa = a;
-        sa.prev_level = l;
-        sa.first_of_level = (q + 1 < seq.size() && seq[q + 1] != l);
-        sa.check_max_iters = (q + 1 == seq.size() && l == 0 && p.stop_update_norm > 0.0);
-        if ((st = launch_solve_batch_list(p.precision, b->d_inst, b->comp, b->comp_list, std::min(n, kListSolveBlocks),
-                                          sa, s)) != UPS_OK)
-            return st;
+        for (int it = 0; it < p.iters[l]; it++) {
+            a.parity = parity;
+            a.first_of_level = it == 0;
+            if ((st = launch_icp_batch_list(b->Ks[l], p.precision, MODE_ITER, b->d_inst_sub, b->comp, b->comp_list,
+                                            b->comp_start + l * (n + 1), n, a,
+                                            std::min(b->total_tiles_sub[l], kListBlocks), s)) != UPS_OK)
+                return st;
+            a.prev_level = l;
+            parity ^= 1;
+        }
     }
     a.level = 0;
+    a.parity = parity;
+    a.first_of_level = 0;
     a.d_max2 = p.d_max[0] * p.d_max[0];
     a.tau2 = a.d_max2;
-    if ((st = launch_icp_batch_list(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->comp, b->comp_list, b->comp_start, n,
-                                    a, std::min(b->total_tiles[0], kListBlocks), s)) != UPS_OK)
+    a.check_max_iters = (p.stop_update_norm > 0.0 && p.iters[0] > 0);
+    if ((st = launch_icp_batch_list(b->Ks[0], p.precision, MODE_EVAL, b->d_inst_sub, b->comp, b->comp_list,
+                                    b->comp_start, n, a, std::min(b->total_tiles_sub[0], kListBlocks), s)) != UPS_OK)
         return st;
-    return launch_finish_batch(p.precision, b->d_inst, n, 0, results_d, s);
+    return launch_finish_batch_list(p.precision, b->d_inst_sub, b->comp, b->comp_list, std::min(n, kListFinishBlocks),
+                                    parity ^ 1, results_d, s);
 }
 
 // A batch call under the persistent scheduler: prepare (states, and pyramids
@@ -607,8 +649,8 @@ ups_status ups_batch_fallback_plan(ups_context *ctx, ups_batch *b, double min_in
     if (count_d && (st = check_ptr(count_d, 4, "count")) != UPS_OK) return st;
     DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
-    return launch_fallback_plan(b->n, results_d, min_inlier_ratio, b->d_tile_start, b->mask, b->comp, b->comp_list,
-                                b->comp_start, count_d, (hipStream_t)stream);
+    return launch_fallback_plan(b->n, results_d, min_inlier_ratio, b->d_tile_start_sub, b->mask, b->comp,
+                                b->comp_list, b->comp_start, count_d, (hipStream_t)stream);
 }
 
 ups_status ups_batch_fallback_run(ups_context *ctx, ups_batch *b, ups_icp_result *results_d, void *stream) {

@@ -234,10 +234,10 @@ ups_status launch_activate_batch(const Inst *insts, int n, hipStream_t s) {
     return UPS_OK;
 }
 
-ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
-                                   const StepArgs &a, hipStream_t s) {
-    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_solve_batch_list<PP>, dim3(blocks), dim3(kBlock), 0, s, insts, hdr,
-                                            list, a))
+ups_status launch_finish_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
+                                    int parity, ups_icp_result *results, hipStream_t s) {
+    UPS_DISPATCH_P(prec, hipLaunchKernelGGL(k_finish_batch_list<PP>, dim3(blocks), dim3(kBlock), 0, s, insts, hdr,
+                                            list, parity, results))
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

@@ -179,8 +179,9 @@ ups_status launch_icp_persistent(int K, int prec, const SchedArgs &A, int blocks
 int persistent_grid(int K, int prec, bool irls);
 // pixels per thread the persistent kernel is instantiated for
 bool persistent_k_supported(int K);
-ups_status launch_solve_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
-                                   const StepArgs &a, hipStream_t s);
+// The results of the listed registrations (state slot `parity`).
+ups_status launch_finish_batch_list(int prec, const Inst *insts, const Compact *hdr, const int *list, int blocks,
+                                    int parity, ups_icp_result *results, hipStream_t s);
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
                                hipStream_t s);
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,

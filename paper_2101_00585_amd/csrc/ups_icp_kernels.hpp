@@ -1025,8 +1025,10 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ i
     icp_block<K, PREC, MODE, FUSED, false, IRLS, false>(insts[lo], a, b - tile_start[lo]);
 }
 
-// A subset of the batch (a Compact list): a fixed grid strides over the
-// subset's tiles, so the launch costs little when the subset is small.
+// A subset of the batch (a Compact list), in the main loop's fused form: a
+// fixed grid strides over the subset's tiles, so the launch costs little when
+// the subset is small, and each tile first applies its registration's
+// pending update (state and partials in ping-pong slots, a.parity).
 template <int K, int PREC, int MODE, bool IRLS>
 __global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restrict__ insts,
                                                            const Compact *__restrict__ hdr,
@@ -1041,44 +1043,11 @@ __global__ __launch_bounds__(kBlock) void k_icp_batch_list(const Inst *__restric
             if (start[mid] <= t) lo = mid;
             else hi = mid;
         }
-        icp_block<K, PREC, MODE, false, false, IRLS>(insts[list[lo]], a, t - start[lo]);
+        __syncthreads();  // the previous tile's state copy (LDS) is no longer read
+        icp_block<K, PREC, MODE, true, false, IRLS, false>(insts[list[lo]], a, t - start[lo]);
     }
 }
 
-// A batch subset, between two Gauss-Newton launches: one block per listed
-// registration reduces the partials of the launch that just ran (if it
-// processed the registration), applies the update, and decides whether the
-// next launch processes the registration.  a.prev_level: level of that launch;
-// a.first_of_level: the next launch starts a new level; a.check_max_iters: it
-// was the last launch of level 0.
-template <int PREC>
-__device__ __forceinline__ void solve_block(const Inst &I, const StepArgs &a) {
-    using Acc = AccOf<PREC>;
-    __shared__ RegState S;
-    __shared__ Acc tot[32];
-    if (threadIdx.x == 0) S = I.state[0];
-    __syncthreads();
-    if (S.active && !S.stop) {
-        reduce_partials<29, Acc>(I.partials, I.pstride, npartials_of(I.nblocks[a.prev_level]), tot);
-        if (threadIdx.x == 0) gn_step<Acc>(a, tot, S);
-    }
-    if (threadIdx.x == 0) {
-        if (a.first_of_level) S.level_active = 1;
-        if (a.check_max_iters && !S.stop && S.level_active) S.status = UPS_MAX_ITERS;
-        S.active = !S.stop && S.level_active;
-        I.state[0] = S;
-    }
-    __syncthreads();  // S is reused when the caller loops
-}
-
-// The registrations of a Compact list only, a small grid striding over them.
-template <int PREC>
-__global__ __launch_bounds__(kBlock) void k_solve_batch_list(const Inst *__restrict__ insts,
-                                                             const Compact *__restrict__ hdr,
-                                                             const int *__restrict__ list, StepArgs a) {
-    const int cnt = hdr->count;
-    for (int m = blockIdx.x; m < cnt; m += gridDim.x) solve_block<PREC>(insts[list[m]], a);
-}
 
 // One block: the evaluation partials -> result (quality at the final pose,
 // plus the state's pose, status, iteration count and last step norm), or ->
@@ -1160,6 +1129,20 @@ template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_finish_batch(const Inst *__restrict__ insts, int parity,
                                                          ups_icp_result *results) {
     finish_block<PREC>(insts[blockIdx.x], parity, results + blockIdx.x, nullptr);
+}
+
+// The results of the registrations of a Compact list only, a small grid
+// striding over them.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_finish_batch_list(const Inst *__restrict__ insts,
+                                                              const Compact *__restrict__ hdr,
+                                                              const int *__restrict__ list, int parity,
+                                                              ups_icp_result *results) {
+    const int cnt = hdr->count;
+    for (int m = blockIdx.x; m < cnt; m += gridDim.x) {
+        __syncthreads();  // the previous registration's totals (LDS) are no longer read
+        finish_block<PREC>(insts[list[m]], parity, results + list[m], nullptr);
+    }
 }
 
 // More than 256 iteration partials: fold them into one before the next

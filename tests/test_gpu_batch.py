@@ -211,7 +211,13 @@ def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs, persistent):
     """Registrations started 60 deg away end with a low inlier ratio and are
     rerun from the identity; the fallback's result replaces theirs (status
     FALLBACK_USED) and matches a plain identity-started registration, while
-    the others keep their results bit for bit."""
+    the others keep their results bit for bit.  Under the launch scheduler the
+    rerun subset is tiled with fewer pixels per thread than the whole batch
+    (more, shorter tiles for a few registrations): the same registration with
+    its sums partitioned differently, so the match is to rounding (pose within
+    1e-6, inliers within 2, truncated cost within those 2 pixels' tau^2);
+    under the persistent scheduler the subset keeps the batch's tiling and
+    matches bit for bit."""
     import torch
     items = _items_from_depth(gpu_lib, pairs[:4])
     b = gpu_lib.Batch(bctx, items, gpu_lib.IcpParams(**BATCH_PARAMS))
@@ -231,8 +237,16 @@ def test_fallback_reruns_only_poor_starts(gpu_lib, bctx, pairs, persistent):
     for k in (0, 2):
         assert first[k]["inlier_ratio"] < 0.5
         assert after[k]["status"] == gpu_lib.STATUS_FALLBACK_USED
-        assert np.array_equal(after[k]["T"], ref[k]["T"])
-        assert after[k]["trunc_cost"] == ref[k]["trunc_cost"]
+        if persistent:
+            assert np.array_equal(after[k]["T"], ref[k]["T"])
+            assert after[k]["trunc_cost"] == ref[k]["trunc_cost"]
+        else:
+            rot, tr = synth.pose_error(after[k]["T"], ref[k]["T"])
+            print(f"\nfallback {k} vs plain: {rot:.2e} rad {tr:.2e} m, inliers {after[k]['inliers']} vs {ref[k]['inliers']}")
+            assert rot < 1e-6 and tr < 1e-6
+            assert abs(after[k]["inliers"] - ref[k]["inliers"]) <= 2
+            tau2 = 0.5 ** 2  # level-0 d_max of the parameters
+            assert abs(after[k]["trunc_cost"] - ref[k]["trunc_cost"]) <= 2 * tau2 + 1e-6 * ref[k]["trunc_cost"]
     for k in (1, 3):
         assert first[k]["inlier_ratio"] >= 0.5
         assert np.array_equal(_np(res)[k], before[k])

@@ -111,7 +111,10 @@ def test_irls_batch_equals_single(gpu_lib, ctx, irls_items):
 def test_irls_batch_subset_path(gpu_lib, ctx, irls_items):
     """The fallback reruns a flagged subset through the list kernels: started
     90 deg off, every registration falls back to the identity start, and the
-    kept result equals the plain identity-started batch result bitwise."""
+    kept result equals the plain identity-started batch result to rounding
+    (the subset is tiled with fewer pixels per thread than the whole batch,
+    so its sums are partitioned differently): pose within 1e-6, inliers
+    within 2."""
     import torch
     params = gpu_lib.IcpParams(**IRLS_BATCH)
     b = gpu_lib.Batch(ctx, irls_items, params)
@@ -123,7 +126,9 @@ def test_irls_batch_subset_path(gpu_lib, ctx, irls_items):
     got = gpu_lib.read_results(out)
     for k in range(n):
         assert got[k]["status"] == gpu_lib.STATUS_FALLBACK_USED, k
-        assert np.array_equal(got[k]["T"], plain[k]["T"]), k
+        rot, tr = synth.pose_error(got[k]["T"], plain[k]["T"])
+        assert rot < 1e-6 and tr < 1e-6, (k, rot, tr)
+        assert abs(got[k]["inliers"] - plain[k]["inliers"]) <= 2, k
     b.close()
 
 
