@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--no-keyframes", action="store_true",
                     help="skip the panorama-formation / keyframe-management measurements")
     ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--proposal-start-level", type=int, default=1,
+                    help="pyramid level the proposal-started registrations start at (the fallback keeps all levels)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--precision", choices=["kahan", "f32", "f64"], default="kahan",
                     help="reduction precision: Kahan FP32 -> FP64, pure FP32, or FP64 accumulation")
@@ -548,7 +550,7 @@ def run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms_pl
     n = len(items)
     prop = ups.Proposal(ctx, n)
     prop.set_params(P.load_params())
-    pr = P.ProposedRegistration(ctx, prop, batch, items)
+    pr = P.ProposedRegistration(ctx, prop, batch, items, start_level=args.proposal_start_level)
     results = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device="cuda")
 
     def step():
@@ -585,7 +587,8 @@ def run_learned(args, torch, ups, synth, ctx, batch, items, pairs, stream, ms_pl
             f"{single['ms_per_batch'] / ms:.1f}x faster")
     return {
         "workload": "the batch above started from the proposal network's poses (BF16 MFMA CNN on 32x256 "
-                    "inverse-range pairs), identity-started fallback below inlier ratio 0.5",
+                    f"inverse-range pairs) at pyramid level {args.proposal_start_level} (coarser levels left out), "
+                    "identity-started fallback (all levels) below inlier ratio 0.5",
         "ms_per_batch": round(ms, 4),
         "registrations_per_s": round(n / ms * 1e3, 1),
         "ms_per_128x1024_equivalent": round(ms / eq128, 5),
@@ -646,7 +649,7 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
     r_plain = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
     r_prop = torch.zeros_like(r_plain)
     r_grid = torch.zeros_like(r_plain)
-    pr = P.ProposedRegistration(ctx, prop, batch, items)
+    pr = P.ProposedRegistration(ctx, prop, batch, items, start_level=args.proposal_start_level)
     # the paper's loop-closure start: 324 candidates scored at pyramid level 2
     gp = ups.GridParams()
     g_scores = torch.empty((n, gp.n_yaw * gp.n_xy * gp.n_xy), dtype=torch.int32, device=dev)
@@ -700,7 +703,8 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
         f"proposal {s_l.sum()}/{n} in {ms_l:.3f} ms ({ms_l1:.3f} ms as one graph), "
         f"grid search {s_g.sum()}/{n} in {ms_g:.3f} ms")
     batch.close()
-    return {"workload": f"{n} held-out pairs, batch sizes and scenes, motions up to {max_deg:.0f} deg / 2 m",
+    return {"workload": f"{n} held-out pairs, batch sizes and scenes, motions up to {max_deg:.0f} deg / 2 m; "
+                        f"proposal-started registrations from pyramid level {args.proposal_start_level}",
             "pixel_iterations_identity_start": px_it(res_p), "pixel_iterations_proposal_start": px_it(res_l),
             "success_within_1deg_5cm_identity_start": int(s_p.sum()),
             "success_within_1deg_5cm_proposal_start": int(s_l.sum()),

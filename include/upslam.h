@@ -465,6 +465,15 @@ enum {
  * effect for calls enqueued afterwards. */
 ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler);
 
+/* Gauss-Newton iterations per pyramid level of later ups_register_batch calls
+ * on this batch (Section III-B's coarse-to-fine schedule; a start already
+ * close to the answer, such as a learned proposal, can leave out the coarsest
+ * levels): iters[l] for l < the batch's levels, each in [0, the value the
+ * batch was created with]; 0 skips the level.  The fallback calls keep the
+ * schedule the batch was created with.  UPS_ERR_INVALID_ARG otherwise.  Host
+ * only; takes effect for calls enqueued afterwards. */
+ups_status ups_batch_set_iterations(ups_batch *b, const int32_t iters[4]);
+
 /* The persistent launch of UPS_SCHED_PERSISTENT: its blocks (the kernel's
  * resident blocks on the device), and the pixels per thread of a tile at each
  * pyramid level. */

@@ -122,6 +122,7 @@ def load():
         "ups_batch_pixels_per_thread": [_P, _P],
         "ups_batch_schedule": [_P, _P, _P],
         "ups_batch_set_scheduler": [_P, ctypes.c_int32],
+        "ups_batch_set_iterations": [_P, _P],
         "ups_debug_reverse_tile_order": [ctypes.c_int32],
         "ups_debug_level_spin_limit": [ctypes.c_int64],
         "ups_splat_sweep": [_P, _P, _P, _P, _P, _P, _P],
@@ -691,6 +692,14 @@ class Batch:
         """Run later register calls as one launch per iteration (False, the
         default) or as one persistent launch (True)."""
         _check(_LIB.ups_batch_set_scheduler(self._h, 1 if persistent else 0))
+
+    def set_iterations(self, iters):
+        """Gauss-Newton iterations per level (finest first) of later register
+        calls, each at most what the batch was created with; 0 skips a level.
+        Fallback calls keep the full schedule."""
+        it = list(iters) + [0] * (4 - len(iters))
+        arr = (ctypes.c_int32 * 4)(*[int(x) for x in it[:4]])
+        _check(_LIB.ups_batch_set_iterations(self._h, ctypes.cast(arr, _P)))
 
     def schedule(self):
         """(blocks of the persistent launch, pixels per thread of a tile per level)."""

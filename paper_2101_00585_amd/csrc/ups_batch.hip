@@ -28,7 +28,8 @@ using namespace ups;
 struct ups_batch {
     int device = 0;
     int n = 0;
-    ups_icp_params p;
+    ups_icp_params p;       // p.iters: the schedule of ups_register_batch calls (ups_batch_set_iterations)
+    int iters_full[4] = {0, 0, 0, 0};  // the schedule the batch was created with (the fallback's)
     int K[4] = {1, 1, 1, 1};
     int total_tiles[4] = {0, 0, 0, 0};
     int total_pre = 0;
@@ -150,6 +151,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     b->device = ctx->device;
     b->n = n;
     b->p = *p;
+    for (int l = 0; l < 4; l++) b->iters_full[l] = p->iters[l];
     for (int l = 0; l < L; l++) {
         int K = pixels_per_thread ? pixels_per_thread : default_k(ctx, max_npix >> (2 * l));
         // every registration must fit in 256 tiles at every level
@@ -421,6 +423,15 @@ ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler) {
     return UPS_OK;
 }
 
+ups_status ups_batch_set_iterations(ups_batch *b, const int32_t iters[4]) {
+    UPS_REQUIRE(b && iters, "null argument");
+    for (int l = 0; l < b->p.levels; l++)
+        UPS_REQUIRE(iters[l] >= 0 && iters[l] <= b->iters_full[l],
+                    "iters[" + std::to_string(l) + "] must be in [0, " + std::to_string(b->iters_full[l]) + "]");
+    for (int l = 0; l < b->p.levels; l++) b->p.iters[l] = iters[l];
+    return UPS_OK;
+}
+
 ups_status ups_batch_schedule(const ups_batch *b, int32_t *blocks, int32_t kpt[4]) {
     UPS_REQUIRE(b && blocks && kpt, "null argument");
     *blocks = b->grid;
@@ -495,7 +506,8 @@ ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_re
 ups_status register_batch_subset(ups_batch *b, const ups_pose *init_d, const uint8_t *mask, ups_icp_result *results_d,
                                  hipStream_t s) {
     ups_status st;
-    const ups_icp_params &p = b->p;
+    ups_icp_params p = b->p;  // the schedule the batch was created with
+    for (int l = 0; l < 4; l++) p.iters[l] = b->iters_full[l];
     const int n = b->n;
     if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, mask, s)) != UPS_OK)
         return st;
@@ -560,7 +572,8 @@ ups_status register_batch_persistent(ups_batch *b, const ups_pose *init_d, const
     A.levels = p.levels;
     for (int l = 0; l < 4; l++) A.kpt[l] = b->kpt[l];
     for (int l = 0; l < 4; l++) {
-        A.iters[l] = l < p.levels ? p.iters[l] : 0;
+        // a fallback call (mask) keeps the schedule the batch was created with
+        A.iters[l] = l < p.levels ? (mask ? b->iters_full[l] : p.iters[l]) : 0;
         A.d_max2[l] = l < p.levels ? p.d_max[l] * p.d_max[l] : 0.f;
     }
     A.cos_theta = p.cos_theta_max;

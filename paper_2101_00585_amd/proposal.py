@@ -353,9 +353,20 @@ class ProposedRegistration:
     The proposal holds one planned input: a later ProposedRegistration (or
     plan_input) on the same Proposal replaces this one's."""
 
-    def __init__(self, ctx: Context, prop: Proposal, batch: Batch, items, min_inlier_ratio=MIN_INLIER_RATIO):
+    def __init__(self, ctx: Context, prop: Proposal, batch: Batch, items, min_inlier_ratio=MIN_INLIER_RATIO,
+                 start_level=None):
         torch = _torch()
         self.batch, self.prop, self.n = batch, prop, len(items)
+        # the proposal-started registrations run the batch's schedule from
+        # `start_level` down (the coarser levels left out); the fallback keeps
+        # the full schedule
+        full = list(batch.params.iters)[:batch.params.levels]
+        if start_level is None:
+            start_level = len(full) - 1
+        if not 0 <= start_level < len(full):
+            raise UpsError("start_level must be one of the batch's pyramid levels")
+        self.full_iters = full
+        self.start_iters = [it if l <= start_level else 0 for l, it in enumerate(full)]
         if self.n > prop.max_batch:
             raise UpsError("batch larger than the proposal's max_batch")
         self.rho = float(min_inlier_ratio)
@@ -378,7 +389,14 @@ class ProposedRegistration:
         self.prop.input()
         self.prop.forward(self.n, None, self.y)
         self.prop.poses(self.y, self.poses)
-        self.batch.register(self.poses, results)
+        if self.start_iters != self.full_iters:
+            self.batch.set_iterations(self.start_iters)
+            try:
+                self.batch.register(self.poses, results)
+            finally:
+                self.batch.set_iterations(self.full_iters)
+        else:
+            self.batch.register(self.poses, results)
         self.batch.fallback_plan(results, self.rho, self.count)
         return results
 

@@ -79,7 +79,7 @@ def arms(request, lib):
     proposed = ups.read_results(pr.run(results))
     torch.cuda.synchronize()
     out = dict(name=request.param, pairs=pairs, plain=plain, started=started, proposed=proposed, b=b, pr=pr,
-               results=results)
+               results=results, items=items)
     s_plain, s_start, s_prop = (_success(r, pairs) for r in (plain, started, proposed))
     n_fb = sum(r["status"] == ups.STATUS_FALLBACK_USED for r in proposed)
     # the rule the inlier-ratio proxy stands in for: fall back when the
@@ -158,3 +158,39 @@ def test_proposed_path_replays_from_a_graph(arms):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(results.cpu().numpy(), eager)
+
+
+def test_start_level_skips_the_coarsest_level(arms, lib):
+    """Proposal-started registrations told to start at level 1 run no level-2
+    iterations, while those the fallback reruns from the identity keep the
+    batch's full schedule; the success thresholds of the full schedule still
+    hold; a schedule longer than the batch was created with is rejected, and
+    the batch's own calls are unchanged afterwards (bitwise)."""
+    import torch
+    from paper_2101_00585_amd import proposal as P
+    ups, ctx, prop = lib
+    b, pairs = arms["b"], arms["pairs"]
+    pr1 = P.ProposedRegistration(ctx, prop, b, arms["items"], RHO_MIN, start_level=1)
+    res = torch.zeros((N_PAIRS, ups.RESULT_BYTES), dtype=torch.uint8, device="cuda")
+    out = ups.read_results(pr1.run(res))
+    torch.cuda.synchronize()
+    n_fb = 0
+    for r in out:
+        if r["status"] == ups.STATUS_FALLBACK_USED:
+            n_fb += 1
+            assert r["level_iters"][2] > 0
+        else:
+            assert r["level_iters"][2] == 0 and r["level_iters"][1] > 0
+    s = _success(out, pairs)
+    print(f"\n{arms['name']} from level 1: success {s.sum()}/{N_PAIRS}, {n_fb} fallbacks used, "
+          f"pixel-iterations {_pixel_iterations(out, pairs) / 1e6:.1f} M")
+    if arms["name"] == "30deg_2m":
+        assert s.mean() >= 0.95
+    else:
+        assert s.sum() >= _success(arms["plain"], pairs).sum() + 0.1 * N_PAIRS
+    with pytest.raises(ups.UpsError):
+        b.set_iterations([10, 10, 11])
+    again = b.register([np.eye(4)] * N_PAIRS)
+    torch.cuda.synchronize()
+    for r, q in zip(ups.read_results(again), arms["plain"]):
+        assert np.array_equal(r["T"], q["T"]) and r["level_iters"] == q["level_iters"]
