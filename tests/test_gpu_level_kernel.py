@@ -119,3 +119,27 @@ def test_level_kernels_on_concurrent_streams(gpu_lib):
         torch.cuda.synchronize()
         for cx in ctxs:
             cx.close()
+
+
+@pytest.mark.parametrize("variant", ["squared", "irls", "world"])
+def test_level_kernel_variants_match_oracle(gpu_lib, ctx, variant):
+    """The instantiations of the one-XCD level kernel (squared objective,
+    IRLS, world-frame arithmetic) on a 64x512 pair, whose levels 2 and 1 each
+    run in one launch, against the oracle's registration on the same FP32
+    surfels: the same iterations per level, the pose within 1e-5 rad / m."""
+    import oracle as O
+    c = W.config0()
+    g = c["geom"]
+    kf = O.panorama_normals(g, c["kf"]).astype(np.float32)
+    scan = O.panorama_normals(g, c["scan"]).astype(np.float32)
+    delta = 0.01 if variant == "irls" else 0.0
+    world = c["T_world_kf"] if variant == "world" else None
+    p = gpu_lib.IcpParams(levels=3, iters=(10, 10, 10), irls_delta=delta)
+    res = gpu_lib.read_result(gpu_lib.register_scan(ctx, g, _t(scan), g, _t(kf), np.eye(4), p, world_kf=world))
+    ref = O.register(g, scan.astype(np.float64), g, kf.astype(np.float64), np.eye(4),
+                     O.IcpParams(levels=3, iters=(10, 10, 10), irls_delta=delta))
+    rot, tr = synth.pose_error(res["T"], ref["T"])
+    print(f"\n{variant}: {rot:.2e} rad {tr:.2e} m, iterations per level {res['level_iters']}")
+    assert res["status"] == ref["status"]
+    assert list(res["level_iters"][:3]) == list(ref["level_iters"][:3])
+    assert rot < 1e-5 and tr < 1e-5
