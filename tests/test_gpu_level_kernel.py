@@ -143,3 +143,68 @@ def test_level_kernel_variants_match_oracle(gpu_lib, ctx, variant):
     assert res["status"] == ref["status"]
     assert list(res["level_iters"][:3]) == list(ref["level_iters"][:3])
     assert rot < 1e-5 and tr < 1e-5
+
+
+def test_level_kernel_beside_a_batch_on_another_stream(gpu_lib):
+    """A single registration (its coarsest level in the one-XCD level kernel,
+    whose workgroups wait for each other) replayed on one stream while a
+    batch of 16 registrations is replayed on another, so that the batch's
+    launches hold the CUs the level kernel's workgroups wait for: both
+    results are bitwise the ones each gives alone, five rounds in a row."""
+    import torch
+    ctx1 = gpu_lib.Context(0, max_pixels=128 * 1024)
+    ctx2 = gpu_lib.Context(0, max_pixels=128 * 1024, max_batch=16, max_batch_pixels=16 * 128 * 1024)
+    try:
+        dev = torch.device("cuda:0")
+        c = W.config0(rows=128, cols=1024)
+        g = c["geom"]
+        kf = gpu_lib.panorama_normals(ctx1, g, _t(c["kf"].astype(np.float32)))
+        scan = gpu_lib.panorama_normals(ctx1, g, _t(c["scan"].astype(np.float32)))
+        p = gpu_lib.IcpParams(levels=3, iters=(10, 10, 10))
+        init_d = gpu_lib.pose_tensor(synth.se3(synth.rot_z(0.02), [0.1, -0.05, 0.0]), dev)
+        items = []
+        for k in range(16):
+            q = W.batch_pair(k, size=(128, 1024), max_angle=np.radians(6), max_trans=0.5)
+            items.append(dict(scan_geom=q["geom"], kf_geom=q["geom"],
+                              scan_surfel=gpu_lib.panorama_normals(ctx2, q["geom"], _t(q["scan"].astype(np.float32))),
+                              kf_surfel=gpu_lib.panorama_normals(ctx2, q["geom"], _t(q["kf"].astype(np.float32)))))
+        b = gpu_lib.Batch(ctx2, items, gpu_lib.IcpParams(levels=3, iters=(10, 10, 10), stop_update_norm=1e-6))
+        binit = torch.stack([gpu_lib.pose_tensor(np.eye(4), dev) for _ in items])
+        r1 = gpu_lib.new_result(dev)
+        r2 = torch.zeros((16, gpu_lib.RESULT_BYTES), dtype=torch.uint8, device=dev)
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        graphs = []
+        for st, fn in ((sa, lambda: gpu_lib.register_scan(ctx1, g, scan, g, kf, init_d, p, r1)),
+                       (sb, lambda: b.register(binit, r2))):
+            with torch.cuda.stream(st):
+                fn()
+            torch.cuda.synchronize()
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=st):
+                fn()
+            graphs.append(gr)
+        # alone
+        refs = []
+        for st, gr, r in ((sa, graphs[0], r1), (sb, graphs[1], r2)):
+            with torch.cuda.stream(st):
+                gr.replay()
+            torch.cuda.synchronize()
+            refs.append(r.cpu().numpy().copy())
+        # together: the batch first, the single registration behind it on the other stream
+        for rnd in range(5):
+            r1.zero_()
+            r2.zero_()
+            torch.cuda.synchronize()
+            print(f"round {rnd}", flush=True)
+            with torch.cuda.stream(sb):
+                graphs[1].replay()
+            with torch.cuda.stream(sa):
+                graphs[0].replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(r1.cpu().numpy(), refs[0]), rnd
+            assert np.array_equal(r2.cpu().numpy(), refs[1]), rnd
+        b.close()
+    finally:
+        torch.cuda.synchronize()
+        ctx1.close()
+        ctx2.close()
