@@ -315,30 +315,36 @@ __device__ __forceinline__ T inv_sqrt(T d) {
     }
 }
 
+// Index of entry (i, j), i <= j, in the row-major upper triangle of a 6x6 matrix.
+__device__ __forceinline__ int tri6(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
+
+// xi = -A^-1 b for the symmetric A given by its row-major upper triangle A21:
+// Cholesky column by column, then forward and back substitution.  A pivot
+// <= 1e-12 x the largest diagonal entry (or no positive diagonal) makes the
+// system DEGENERATE; the pivots are checked once after the factorisation (a
+// failed pivot only yields values that are then discarded), so that no
+// branch splits the dependent chain.
 template <typename T>
 __device__ int cholesky_solve6(const T *A21, const T *b, T *xi) {
-    T A[6][6], L[6][6], inv[6];
-    int e = 0;
-    for (int a = 0; a < 6; a++)
-        for (int c = a; c < 6; c++) {
-            A[a][c] = A21[e];
-            A[c][a] = A21[e];
-            e++;
-        }
+    T L[6][6], inv[6];
     T maxd = 0;
-    for (int a = 0; a < 6; a++) maxd = A[a][a] > maxd ? A[a][a] : maxd;
-    if (!(maxd > T(0))) return UPS_DEGENERATE;
+    for (int a = 0; a < 6; a++) {
+        const T v = A21[tri6(a, a)];
+        maxd = v > maxd ? v : maxd;
+    }
+    bool ok = maxd > T(0);
     for (int c = 0; c < 6; c++) {
-        T d = A[c][c];
+        T d = A21[tri6(c, c)];
         for (int k = 0; k < c; k++) d -= L[c][k] * L[c][k];
-        if (!(d > T(1e-12) * maxd)) return UPS_DEGENERATE;
+        ok = ok && (d > T(1e-12) * maxd);
         inv[c] = inv_sqrt<T>(d);  // 1 / L[c][c]
         for (int r = c + 1; r < 6; r++) {
-            T s = A[r][c];
+            T s = A21[tri6(c, r)];
             for (int k = 0; k < c; k++) s -= L[r][k] * L[c][k];
             L[r][c] = s * inv[c];
         }
     }
+    if (!ok) return UPS_DEGENERATE;
     T y[6];
     for (int r = 0; r < 6; r++) {
         T s = -b[r];
@@ -451,9 +457,6 @@ __device__ __forceinline__ T lane_fetch(T v, int src) {
         return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
     }
 }
-
-// Index of entry (i, j), i <= j, in the row-major upper triangle of a 6x6 matrix.
-__device__ __forceinline__ int tri6(int i, int j) { return i * 6 - (i * (i - 1)) / 2 + (j - i); }
 
 // Gauss-Newton step from the reduced totals (J^T J upper triangle in tot[0..20],
 // J^T r in tot[21..26], inlier count in tot[28]), computed by one whole
