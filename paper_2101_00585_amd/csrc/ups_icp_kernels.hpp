@@ -240,6 +240,36 @@ __device__ __forceinline__ void block_partial(const Acc (&x)[NV], Acc (*qbuf)[65
     }
 }
 
+// The block's sum of NV per-thread values through one LDS transpose (single
+// registrations, one block per CU, so the 64 KB buffer costs no occupancy):
+// every thread stores its NV values, then the 8 threads of value v add the
+// 256 values in a fixed order -- thread g the 32 values of threads g, g + 8,
+// ..., g + 248 as a pairwise tree -- and oct_sum combines the 8.  Rows are
+// padded by 8 values so that a wavefront's reads spread over the banks.
+// COH: the partial stored as agent-coherent words.
+template <int NV, typename Acc, bool COH = false>
+__device__ __forceinline__ void block_partial_lds(const Acc (&x)[NV], double *part_out, int pstride, int tile) {
+    constexpr int kRow = kBlock + 8;
+    __shared__ Acc buf[NV * kRow];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; v++) buf[v * kRow + tid] = x[v];
+    __syncthreads();
+    const int v = min(tid >> 3, NV - 1), g = tid & 7;
+    Acc y[32];
+#pragma unroll
+    for (int k = 0; k < 32; k++) y[k] = buf[v * kRow + g + 8 * k];
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1)
+#pragma unroll
+        for (int k = 0; k < w; k++) y[k] += y[k + w];
+    const Acc t = oct_sum<Acc>(y[0]);
+    if (g == 0 && (tid >> 3) < NV) {
+        if constexpr (COH) st_coh_d(part_out + (size_t)v * pstride + tile, (double)t);
+        else part_out[(size_t)v * pstride + tile] = (double)t;
+    }
+}
+
 typedef double v2d __attribute__((ext_vector_type(2)));
 
 // Value v = tid / 8 (clamped to NV - 1) summed over the first n block
@@ -866,7 +896,10 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
         Acc x[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) x[v] = (Acc)acc.get(v);
-        block_partial<NV, Acc, MODE == MODE_SCHED || COH>(x, qbuf, part_out, I.pstride, tile, tot);
+        if constexpr (STRIDED && MODE != MODE_SCHED)
+            block_partial_lds<NV, Acc, COH>(x, part_out, I.pstride, tile);
+        else
+            block_partial<NV, Acc, MODE == MODE_SCHED>(x, qbuf, part_out, I.pstride, tile, tot);
     }
     UPS_PHASE(kPh, tile, a.seq, 4);
     if (FUSED && tile == 0) {
