@@ -10,13 +10,13 @@ namespace ups {
 // last row: the normalised cross product of the two difference vectors,
 // oriented towards the sensor; zero when a range is invalid, a neighbour jumps
 // by more than max_rel_jump * rc, or the cross product is degenerate.
-__device__ __forceinline__ float3 raw_normal(const DGeom &g, int i, int j, int ib, float rc, float ra, float rb,
-                                             float max_rel_jump) {
+// The same from the rays of the three pixels (uc: the pixel, ua: its right
+// neighbour, ub: the lower one); ib < 0 means the lower neighbour is missing.
+__device__ __forceinline__ float3 raw_normal_rays(const DGeom &g, int ib, float rc, float ra, float rb, float3 uc,
+                                                  float3 ua, float3 ub, float max_rel_jump) {
     float3 o = make_float3(0.f, 0.f, 0.f);
     if (!(range_ok(g, rc) && ib >= 0 && range_ok(g, ra) && range_ok(g, rb))) return o;
     if (fabsf(ra - rc) > max_rel_jump * rc || fabsf(rb - rc) > max_rel_jump * rc) return o;
-    const int ja = (j + 1 == g.cols) ? 0 : j + 1;
-    const float3 uc = ray(g, i, j), ua = ray(g, i, ja), ub = ray(g, ib, j);
     const float3 pc = make_float3(rc * uc.x, rc * uc.y, rc * uc.z);
     const float3 a = make_float3(ra * ua.x - pc.x, ra * ua.y - pc.y, ra * ua.z - pc.z);
     const float3 b = make_float3(rb * ub.x - pc.x, rb * ub.y - pc.y, rb * ub.z - pc.z);
@@ -27,6 +27,16 @@ __device__ __forceinline__ float3 raw_normal(const DGeom &g, int i, int j, int i
     const float s = (dot3(n, pc) > 0.f) ? -inv : inv;
     return make_float3(n.x * s, n.y * s, n.z * s);
 }
+
+__device__ __forceinline__ float3 raw_normal(const DGeom &g, int i, int j, int ib, float rc, float ra, float rb,
+                                             float max_rel_jump) {
+    if (!(range_ok(g, rc) && ib >= 0 && range_ok(g, ra) && range_ok(g, rb))) return make_float3(0.f, 0.f, 0.f);
+    const int ja = (j + 1 == g.cols) ? 0 : j + 1;
+    return raw_normal_rays(g, ib, rc, ra, rb, ray(g, i, j), ray(g, i, ja), ray(g, ib, j), max_rel_jump);
+}
+
+// Ray of a pixel from its row's (cos el, sin el) and its column's (cos az, sin az).
+__device__ __forceinline__ float3 ray_of(float2 e, float2 a) { return make_float3(e.x * a.x, e.x * a.y, e.y); }
 
 // Raw normals only (no smoothing): one thread per pixel; the neighbour reads
 // are served from L1/L2.
@@ -103,16 +113,17 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
     return o;
 }
 
-// One a-trous level with taps spaced `step` for the 16 x 64 output tile at
-// (x0, y0): the block stages the (16 + 4 step) x (64 + 4 step) surfel tile
-// around it in LDS (rows outside the image empty, columns wrapped), four
-// outputs per thread.
-template <int kTileH>
+// One a-trous level with taps spaced STEP for the kTileH x 64 output tile at
+// (x0, y0): the block stages the (kTileH + 4 STEP) x (64 + 4 STEP) surfel
+// tile around it in LDS (rows outside the image empty, columns wrapped), one
+// output row per wavefront and pass.  STEP is a template parameter so that
+// the staging loop divides by a constant and every tap reads LDS at a
+// constant offset from the output's address.
+template <int kTileH, int STEP>
 __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__restrict__ in, float4 *__restrict__ out,
-                                            int x0, int y0, int step, float inv_sigma_r, float inv_sigma_n2,
-                                            float4 *tile) {
-    const int halo = 2 * step;
-    const int LW = kTileW + 2 * halo, LH = kTileH + 2 * halo;
+                                            int x0, int y0, float inv_sigma_r, float inv_sigma_n2, float4 *tile) {
+    constexpr int halo = 2 * STEP;
+    constexpr int LW = kTileW + 2 * halo, LH = kTileH + 2 * halo;
     for (int idx = threadIdx.x; idx < LW * LH; idx += kBlock) {
         const int ly = idx / LW, lx = idx - ly * LW;
         const int gy = y0 - halo + ly;
@@ -127,15 +138,19 @@ __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__rest
     for (int ty = threadIdx.x / kTileW; ty < kTileH; ty += kBlock / kTileW) {
         const int gy = y0 + ty;
         if (gy >= g.rows) break;
-        out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, step, inv_sigma_r, inv_sigma_n2);
+        out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, STEP, inv_sigma_r, inv_sigma_n2);
     }
 }
 
+template <int kTileH, int STEP>
+constexpr int atrous_tile_elems() { return (kTileW + 4 * STEP) * (kTileH + 4 * STEP); }
+
+template <int STEP>
 __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__restrict__ in, float4 *__restrict__ out,
-                                                   int step, float inv_sigma_r, float inv_sigma_n2) {
-    extern __shared__ float4 tile[];
-    atrous_tile<kTileHOne>(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, step, inv_sigma_r, inv_sigma_n2,
-                           tile);
+                                                   float inv_sigma_r, float inv_sigma_n2) {
+    __shared__ float4 tile[atrous_tile_elems<kTileHOne, STEP>()];
+    atrous_tile<kTileHOne, STEP>(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, inv_sigma_r, inv_sigma_n2,
+                                 tile);
 }
 
 // Raw normals and the first a-trous level (step 1) in one pass: the block
@@ -148,8 +163,19 @@ __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float 
                                                     float inv_sigma_r, float inv_sigma_n2) {
     constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
     constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
+    static_assert(kDH + kDW <= kBlock, "ray tables of the tile: one entry per thread");
     __shared__ float rng[kDH][kDW];
+    __shared__ float2 lrow[kDH], lcol[kDW];  // ray tables of the range tile's rows and columns
     __shared__ float4 raw[kFH * kFW];
+    if (threadIdx.x < kDH) {
+        const int gy = y0 - 3 + (int)threadIdx.x;
+        lrow[threadIdx.x] = (gy >= 0 && gy < g.rows) ? ldg(g.lut_row, gy * g.stride) : make_float2(0.f, 0.f);
+    } else if (threadIdx.x < kDH + kDW) {
+        const int lx = threadIdx.x - kDH;
+        int gx = x0 - 2 + lx;
+        gx = gx < 0 ? gx + g.cols : (gx >= g.cols ? gx - g.cols : gx);
+        lcol[lx] = ldg(g.lut_col, gx * g.stride);
+    }
     // ranges of rows y0-3 .. y0+kTileH+2 and columns x0-2 .. x0+kTileW+2
     for (int idx = threadIdx.x; idx < kDH * kDW; idx += kBlock) {
         const int ly = idx / kDW, lx = idx - ly * kDW;
@@ -170,8 +196,10 @@ __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float 
             const int dy = ly + 1, dx = lx;  // this pixel in the range tile
             const float rc = rng[dy][dx];
             const int ib = (gy + 1 < g.rows) ? gy + 1 : gy - 1;
-            const float rb = (ib == gy + 1) ? rng[dy + 1][dx] : rng[dy - 1][dx];
-            const float3 n = raw_normal(g, gy, gx, ib, rc, rng[dy][dx + 1], rb, max_rel_jump);
+            const int db = (ib == gy + 1) ? dy + 1 : dy - 1;  // the lower neighbour's row in the range tile
+            const float3 n = raw_normal_rays(g, ib, rc, rng[dy][dx + 1], rng[db][dx], ray_of(lrow[dy], lcol[dx]),
+                                             ray_of(lrow[dy], lcol[dx + 1]), ray_of(lrow[db], lcol[dx]),
+                                             max_rel_jump);
             v = make_float4(n.x, n.y, n.z, range_ok(g, rc) ? rc : 0.f);
         }
         raw[idx] = v;
@@ -216,16 +244,17 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *
                                      max_rel_jump, inv_sigma_r, inv_sigma_n2);
 }
 
+template <int STEP>
 __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restrict__ imgs,
                                                          const int *__restrict__ tile_start, int n, int src_tmp,
-                                                         int step, float inv_sigma_r, float inv_sigma_n2) {
-    extern __shared__ float4 tile[];
+                                                         float inv_sigma_r, float inv_sigma_n2) {
+    __shared__ float4 tile[atrous_tile_elems<kTileHBatch, STEP>()];
     const int k = find_image(tile_start, n, blockIdx.x);
     const NormImg &im = imgs[k];
     const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
-    atrous_tile<kTileHBatch>(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW,
-                             by * kTileHBatch, step, inv_sigma_r, inv_sigma_n2, tile);
+    atrous_tile<kTileHBatch, STEP>(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW,
+                                   by * kTileHBatch, inv_sigma_r, inv_sigma_n2, tile);
 }
 
 // Tiles of a panorama in the batched a-trous launches.
@@ -248,10 +277,13 @@ ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int 
                        p.max_rel_jump, inv_sr, inv_sn2);
     UPS_CHECK_HIP(hipGetLastError());
     for (int l = 1; l < L; l++) {
-        const int step = 1 << l;
-        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileHBatch + 4 * step) * sizeof(float4);
-        hipLaunchKernelGGL(k_atrous_batch, dim3(total_tiles), dim3(kBlock), lds, s, imgs, tile_start, n, in_tmp, step,
-                           inv_sr, inv_sn2);
+        // levels 1 and 2 (taps spaced 2 and 4); the caller limits the levels to 3
+        if (l == 1)
+            hipLaunchKernelGGL(k_atrous_batch<2>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+                               inv_sr, inv_sn2);
+        else
+            hipLaunchKernelGGL(k_atrous_batch<4>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+                               inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         in_tmp ^= 1;
     }
@@ -278,9 +310,9 @@ ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, 
     const float4 *src = dst;
     for (int l = 1; l < L; l++) {
         dst = bufs[(L - 1 - l) % 2];
-        const int step = 1 << l;
-        const size_t lds = (size_t)(kTileW + 4 * step) * (kTileHOne + 4 * step) * sizeof(float4);
-        hipLaunchKernelGGL(k_atrous, grid, dim3(kBlock), lds, s, g, src, dst, step, inv_sr, inv_sn2);
+        // levels 1 and 2 (taps spaced 2 and 4); the caller limits the levels to 3
+        if (l == 1) hipLaunchKernelGGL(k_atrous<2>, grid, dim3(kBlock), 0, s, g, src, dst, inv_sr, inv_sn2);
+        else hipLaunchKernelGGL(k_atrous<4>, grid, dim3(kBlock), 0, s, g, src, dst, inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         src = dst;
     }
