@@ -73,25 +73,27 @@ struct PropItem {
 // x[b][y][x][c] = bf16(1/r) of pixel (y rows/32, x cols/256) of image c, 0
 // where the range is not valid.
 // A block covers 256 pixels of one pair, so the pair's descriptor is
-// block-uniform (scalar loads).
-__global__ __launch_bounds__(256) void k_prop_input(const PropItem *__restrict__ items, int n, uint16_t *__restrict__ x) {
+// block-uniform (scalar loads); both images' ranges are loaded before
+// either is used, and the two channels of a pixel go out as one 4-byte store.
+__device__ __forceinline__ uint32_t prop_inv_range_bf16(const RangeImg &im, float r) {
+    const bool ok = isfinite(r) && r > im.r_min && r <= im.r_max;
+    const float v = ok ? 1.0f / r : 0.0f;
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__global__ __launch_bounds__(256) void k_prop_input(const PropItem *__restrict__ items, int n, uint32_t *__restrict__ x) {
     static_assert((kRows * kCols) % 256 == 0, "a block covers pixels of one pair");
+    static_assert(kIn == 2, "two channels per 4-byte store");
     constexpr int kBlocksPerPair = kRows * kCols / 256;
     const int b = blockIdx.x / kBlocksPerPair;
     if (b >= n) return;
     const int q = (blockIdx.x - b * kBlocksPerPair) * 256 + threadIdx.x, y = q / kCols, xx = q - y * kCols;
-    const int i = b * (kRows * kCols) + q;
-#pragma unroll
-    for (int c = 0; c < kIn; c++) {
-        const RangeImg &im = items[b].img[c];
-        const int fy = im.rows / kRows, fx = im.cols / kCols;
-        const float r = im.r[((size_t)(y * fy) * im.cols + (size_t)xx * fx) * im.stride];
-        const bool ok = isfinite(r) && r > im.r_min && r <= im.r_max;
-        const float v = ok ? 1.0f / r : 0.0f;
-        uint32_t u = __float_as_uint(v);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        x[(size_t)i * kIn + c] = (uint16_t)(u >> 16);
-    }
+    const RangeImg &kf = items[b].img[0], &sc = items[b].img[1];
+    const float r0 = kf.r[((size_t)(y * (kf.rows / kRows)) * kf.cols + (size_t)xx * (kf.cols / kCols)) * kf.stride];
+    const float r1 = sc.r[((size_t)(y * (sc.rows / kRows)) * sc.cols + (size_t)xx * (sc.cols / kCols)) * sc.stride];
+    x[(size_t)b * (kRows * kCols) + q] = prop_inv_range_bf16(kf, r0) | (prop_inv_range_bf16(sc, r1) << 16);
 }
 
 // pose[b] = (Exp(S_omega y[0:3]), S_t y[3:6]) in FP64 (Rodrigues).
@@ -425,7 +427,7 @@ ups_status ups_proposal_input(ups_proposal *p, uint16_t *x_d, void *stream) {
     UPS_CHECK_HIP(g.err);
     const int total = p->n_items * kRows * kCols;
     hipLaunchKernelGGL(k_prop_input, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream, p->d_items,
-                       p->n_items, x);
+                       p->n_items, (uint32_t *)x);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

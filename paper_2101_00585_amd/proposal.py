@@ -351,7 +351,10 @@ class ProposedRegistration:
     ``min_inlier_ratio``.  ``run`` enqueues only kernels (input, network,
     poses, registration, fallback), so it can be captured in a HIP graph.
     The proposal holds one planned input: a later ProposedRegistration (or
-    plan_input) on the same Proposal replaces this one's."""
+    plan_input) on the same Proposal replaces this one's.  The scan channel
+    is read from an item's ``scan_depth`` when it has one (the same valid
+    ranges as its surfels' range channel, 4 bytes per sample instead of a
+    16-byte surfel), else from ``scan_surfel``."""
 
     def __init__(self, ctx: Context, prop: Proposal, batch: Batch, items, min_inlier_ratio=MIN_INLIER_RATIO,
                  start_level=None):
@@ -370,7 +373,8 @@ class ProposedRegistration:
         if self.n > prop.max_batch:
             raise UpsError("batch larger than the proposal's max_batch")
         self.rho = float(min_inlier_ratio)
-        prop.plan_input([it["kf_surfel"] for it in items], [it["scan_surfel"] for it in items],
+        prop.plan_input([it["kf_surfel"] for it in items],
+                        [it["scan_depth"] if it.get("scan_depth") is not None else it["scan_surfel"] for it in items],
                         [it["kf_geom"] for it in items], [it["scan_geom"] for it in items])
         self.y = torch.empty((self.n, 6), dtype=torch.float32, device="cuda")
         self.poses = torch.empty((self.n, 12), dtype=torch.float64, device="cuda")

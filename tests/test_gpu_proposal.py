@@ -194,3 +194,24 @@ def test_start_level_skips_the_coarsest_level(arms, lib):
     torch.cuda.synchronize()
     for r, q in zip(ups.read_results(again), arms["plain"]):
         assert np.array_equal(r["T"], q["T"]) and r["level_iters"] == q["level_iters"]
+
+
+def test_scan_channel_from_depth_equals_surfel_range(arms, lib):
+    """ProposedRegistration reads the network's scan channel from the items'
+    depth images; read from the scans' surfels instead (their range channel
+    holds the same range wherever it is valid) the input is bitwise the
+    same."""
+    import torch
+    ups, ctx, prop = lib
+    items = arms["items"]
+    kf = [it["kf_surfel"] for it in items]
+    geoms = [it["kf_geom"] for it in items], [it["scan_geom"] for it in items]
+    xs = []
+    for key in ("scan_depth", "scan_surfel"):
+        prop.plan_input(kf, [it[key] for it in items], *geoms)
+        x = torch.empty((N_PAIRS, 32, 256, 2), dtype=torch.bfloat16, device="cuda")
+        prop.input(x)
+        xs.append(x)
+    torch.cuda.synchronize()
+    assert torch.equal(xs[0].view(torch.int16), xs[1].view(torch.int16))
+    assert int((xs[0].view(torch.int16)[..., 1] != 0).sum()) > N_PAIRS * 32 * 256 // 4  # mostly valid ranges
