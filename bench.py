@@ -311,6 +311,9 @@ def run_batch(args, torch, ups, synth, W, stream):
     torch.cuda.synchronize()
     params = ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6, precision=PREC[args.precision])
     batch = ups.Batch(ctx, items, params)
+    # the scans' pyramid levels come from the normals' last pass; the register
+    # call builds only the resident keyframes'
+    batch.set_pyramid_mode(True)
     init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
     results = torch.zeros((N_BATCH, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
 
@@ -354,7 +357,8 @@ def run_batch(args, torch, ups, synth, W, stream):
     out = {
         "workload": f"{N_BATCH} registrations, sizes from 64x512/64x1024/128x1024/128x2048, identity start, "
                     "3 levels <=10/10/10, early exit 1e-6; each step computes the 256 scans' surfels and "
-                    "registers them to resident keyframe surfel panoramas",
+                    "registers them to resident keyframe surfel panoramas; the scans' pyramid levels are "
+                    "written by the normals' last pass, the keyframes' by the register call",
         "ms_per_batch": round(ms, 4),
         "ms_scan_normals": round(ms_normals, 4),
         "ms_register": round(ms_register, 4),
@@ -391,6 +395,8 @@ def run_irls(args, torch, ups, synth, ctx, items, pairs, stream, ms_register, la
     delta = 0.01
     params = ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6, irls_delta=delta)
     b = ups.Batch(ctx, items, params)
+    b.set_pyramid_mode(True)  # as the squared objective's batch: the scans' pyramids come with its normals
+    b.normals()
     init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
     results = torch.zeros((N_BATCH, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
     b.register(init, results)
@@ -645,6 +651,7 @@ def run_wide(args, torch, ups, synth, ctx, prop, stream, max_deg, seed, n=256):
                           scan_surfel=torch.empty((g.rows, g.cols, 4), dtype=torch.float32, device=dev)))
     torch.cuda.synchronize()
     batch = ups.Batch(ctx, items, ups.IcpParams(levels=LEVELS, iters=ITERS, stop_update_norm=1e-6))
+    batch.set_pyramid_mode(True)  # every arm starts with the normals call, which writes the scans' pyramids
     init = torch.stack([ups.pose_tensor(np.eye(4), dev) for _ in pairs])
     r_plain = torch.zeros((n, ups.RESULT_BYTES), dtype=torch.uint8, device=dev)
     r_prop = torch.zeros_like(r_plain)

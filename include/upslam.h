@@ -349,9 +349,10 @@ ups_status ups_normal_equations(ups_context *ctx, const ups_geom *scan_g, const 
  * candidate transforms of a loop-closure search, Section III-C) advanced
  * together.  Two schedulers, chosen per batch (ups_batch_set_scheduler):
  *   UPS_SCHED_LAUNCHES (default): one launch per Gauss-Newton iteration covers
- *     every registration of the batch, one small launch per iteration solves
- *     and updates them; a registration that met its stop criterion or failed
- *     drops out of the remaining launches (its blocks exit at once).
+ *     every registration of the batch, each block first applying its
+ *     registration's update from the previous launch's sums; a registration
+ *     that met its stop criterion or failed drops out of the remaining
+ *     launches (its blocks exit at once).
  *   UPS_SCHED_PERSISTENT: one persistent launch in which each registration
  *     advances through its iterations as its own chain of jobs (the tiles of
  *     an iteration, then the update by the block that finishes the last
@@ -385,7 +386,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
 void ups_batch_destroy(ups_batch *b);
 
 /* Surfel images (Section III-A) of every item that has depth pointers, one
- * launch per a-trous level over all of them. */
+ * launch per a-trous level over all of them (in UPS_PYR_IN_NORMALS mode also
+ * the batch's pyramids, see ups_batch_set_pyramid_mode). */
 ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_params *p, void *stream);
 
 /* Run every registration of the batch from init_d[n] (device poses) and write
@@ -464,6 +466,24 @@ enum {
  * batch (UPS_SCHED_*; UPS_ERR_INVALID_ARG otherwise).  Host only; takes
  * effect for calls enqueued afterwards. */
 ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler);
+
+enum {
+    UPS_PYR_IN_REGISTER = 0, /* ups_register_batch builds the pyramids (default) */
+    UPS_PYR_IN_NORMALS = 1   /* ups_batch_normals builds them */
+};
+
+/* Where the batch's pyramid levels 1 and up (subsampled copies of every scan
+ * and keyframe surfel image that the coarse Gauss-Newton levels read) are
+ * built.  UPS_PYR_IN_REGISTER (default): every ups_register_batch and
+ * ups_batch_grid_search call builds them from the level-0 surfel images.
+ * UPS_PYR_IN_NORMALS: the last a-trous pass of ups_batch_normals also writes
+ * the pyramid levels of every image it computes (the items' images with
+ * depth), and register and grid-search calls build only those of the other
+ * images (surfel images the batch reads as they are, such as resident
+ * keyframes): call ups_batch_normals after any change to the depth of an
+ * item.  The results are the same either way.  UPS_ERR_INVALID_ARG for
+ * another mode.  Host only; takes effect for calls enqueued afterwards. */
+ups_status ups_batch_set_pyramid_mode(ups_batch *b, int32_t mode);
 
 /* Gauss-Newton iterations per pyramid level of later ups_register_batch calls
  * on this batch (Section III-B's coarse-to-fine schedule; a start already

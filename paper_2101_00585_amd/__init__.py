@@ -123,6 +123,7 @@ def load():
         "ups_batch_schedule": [_P, _P, _P],
         "ups_batch_set_scheduler": [_P, ctypes.c_int32],
         "ups_batch_set_iterations": [_P, _P],
+        "ups_batch_set_pyramid_mode": [_P, ctypes.c_int32],
         "ups_debug_reverse_tile_order": [ctypes.c_int32],
         "ups_debug_level_spin_limit": [ctypes.c_int64],
         "ups_splat_sweep": [_P, _P, _P, _P, _P, _P, _P],
@@ -692,6 +693,14 @@ class Batch:
         """Run later register calls as one launch per iteration (False, the
         default) or as one persistent launch (True)."""
         _check(_LIB.ups_batch_set_scheduler(self._h, 1 if persistent else 0))
+
+    def set_pyramid_mode(self, in_normals):
+        """True: the last pass of ``normals`` also writes the pyramid levels of
+        the images it computes, and later register and grid-search calls
+        build only those of the other images (surfels given as they are);
+        False (the default): every register / grid-search call builds them
+        all.  The same results either way."""
+        _check(_LIB.ups_batch_set_pyramid_mode(self._h, 1 if in_normals else 0))
 
     def set_iterations(self, iters):
         """Gauss-Newton iterations per level (finest first) of later register

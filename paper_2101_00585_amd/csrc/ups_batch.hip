@@ -61,6 +61,14 @@ struct ups_batch {
     int *d_tile_start_sub = nullptr;   // [4][n+1]
     double *partials_sub = nullptr;    // [n][2][kPartialStride][pstride of the subset tiles]
     int scheduler = UPS_SCHED_LAUNCHES;
+    // where the pyramid levels are built (UPS_PYR_*); in UPS_PYR_IN_NORMALS
+    // mode the normals' last pass writes those of the images it computes, and
+    // register / grid-search calls build only the others (need[k]: bit 0 the
+    // scan, bit 1 the keyframe has no depth)
+    int pyr_mode = UPS_PYR_IN_REGISTER;
+    uint8_t *d_need = nullptr;           // [n]
+    int *d_pre_need_start = nullptr;     // [n+1] prefix table of those images' level-1 pixels
+    int total_pre_need = 0;
     // persistent scheduler
     int Kp = 0;                       // the persistent kernel's pixels per thread (the largest of kpt)
     int kpt[4] = {1, 1, 1, 1};        // pixels per thread of its tiles at each level
@@ -101,6 +109,8 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->tile_map);
     (void)hipFree(b->jobs);
     (void)hipFree(b->arrived);
+    (void)hipFree(b->d_need);
+    (void)hipFree(b->d_pre_need_start);
     delete b;
 }
 
@@ -109,6 +119,20 @@ void free_batch(ups_batch *b) {
 int default_k(ups_context *ctx, int64_t npix) {
     const int tuned = autotuned_k(ctx, npix);
     return tuned > 0 ? tuned : 8;
+}
+
+// The pyramids a register / grid-search call builds: every image's, or in
+// UPS_PYR_IN_NORMALS mode those of the images without depth (the normals
+// write the others): prefix table of their level-1 pixels, its total, and
+// the per-registration selection (null: every image).
+struct PyrWork {
+    const int *start;
+    int total;
+    const uint8_t *need;
+};
+PyrWork pyramid_work(const ups_batch *b) {
+    if (b->pyr_mode == UPS_PYR_IN_NORMALS) return PyrWork{b->d_pre_need_start, b->total_pre_need, b->d_need};
+    return PyrWork{b->d_pre_start, b->total_pre, nullptr};
 }
 
 }  // namespace
@@ -183,6 +207,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     // host descriptors
     std::vector<Inst> hi(n);
     std::vector<int> tile_start(4 * (n + 1), 0), tile_start_sub(4 * (n + 1), 0), pre_start(n + 1, 0);
+    std::vector<int> pre_need_start(n + 1, 0);
+    std::vector<uint8_t> need(n, 0);
     std::vector<int> nblocks_sub(4 * (size_t)n, 0);
     int64_t pyr_total = 0;
     int pstride = 1, pstride_sub = 1;
@@ -204,8 +230,13 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
             pstride = std::max(pstride, I.nblocks[l]);
             nblocks_sub[4 * k + l] = (np + kBlock * b->Ks[l] - 1) / (kBlock * b->Ks[l]);
             pstride_sub = std::max(pstride_sub, nblocks_sub[4 * k + l]);
-            if (l == 1) pre += np + I.kg[l].rows * I.kg[l].cols;
+            if (l == 1) {
+                pre += np + I.kg[l].rows * I.kg[l].cols;
+                need[k] = (uint8_t)((it.scan_depth_d ? 0 : 1) | (it.kf_depth_d ? 0 : 2));
+                pre_need_start[k + 1] = (need[k] & 1 ? np : 0) + (need[k] & 2 ? I.kg[l].rows * I.kg[l].cols : 0);
+            }
         }
+        pre_need_start[k + 1] += pre_need_start[k];
         pyr_off_s[k] = pyr_total;
         for (int l = 1; l < L; l++) pyr_total += (int64_t)I.sg[l].rows * I.sg[l].cols;
         pyr_off_k[k] = pyr_total;
@@ -221,6 +252,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         b->total_tiles_sub[l] = tile_start_sub[l * (n + 1) + n];
     }
     b->total_pre = pre_start[n];
+    b->total_pre_need = pre_need_start[n];
     // tickets of a call, at most: every iteration of every level of every
     // registration, plus the last ticket of each block
     {
@@ -242,16 +274,19 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
 
     // batched-normals images: every scan / keyframe with a depth pointer
     std::vector<NormImg> nimg;
+    std::vector<std::pair<int, int>> nimg_of;  // (registration, 0 scan / 1 keyframe) of each entry
     std::vector<int> ntile_start(1, 0);
     int64_t ntmp_total = 0;
     for (int k = 0; k < n; k++) {
         const ups_batch_item &it = items[k];
         if (it.scan_depth_d) {
-            nimg.push_back(NormImg{hi[k].sg[0], it.scan_depth_d, (float4 *)it.scan_surfel_d, nullptr});
+            nimg.push_back(NormImg{hi[k].sg[0], it.scan_depth_d, (float4 *)it.scan_surfel_d, nullptr, {}});
+            nimg_of.emplace_back(k, 0);
             ntmp_total += (int64_t)hi[k].sg[0].rows * hi[k].sg[0].cols;
         }
         if (it.kf_depth_d) {
-            nimg.push_back(NormImg{hi[k].kg[0], it.kf_depth_d, (float4 *)it.kf_surfel_d, nullptr});
+            nimg.push_back(NormImg{hi[k].kg[0], it.kf_depth_d, (float4 *)it.kf_surfel_d, nullptr, {}});
+            nimg_of.emplace_back(k, 1);
             ntmp_total += (int64_t)hi[k].kg[0].rows * hi[k].kg[0].cols;
         }
     }
@@ -279,6 +314,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     alloc((void **)&b->tile_map, (size_t)b->map_size * sizeof(unsigned long long));
     alloc((void **)&b->jobs, (size_t)n * sizeof(SchedJob));
     alloc((void **)&b->arrived, (size_t)n * sizeof(int));
+    alloc((void **)&b->d_need, (size_t)n);
+    alloc((void **)&b->d_pre_need_start, pre_need_start.size() * sizeof(int));
     if (e == hipSuccess) {
         b->comp_list = (int *)((char *)b->comp + 64);
         b->comp_start = b->comp_list + n;
@@ -317,7 +354,11 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     }
     if (!nimg.empty()) {
         int64_t off = 0;
-        for (auto &im : nimg) {
+        for (size_t m = 0; m < nimg.size(); m++) {
+            NormImg &im = nimg[m];
+            const Inst &I = hi[nimg_of[m].first];
+            for (int l = 1; l <= 3; l++)
+                im.pyr[l - 1] = l < L ? (float4 *)(nimg_of[m].second == 0 ? I.scan[l] : I.kf[l]) : nullptr;
             im.tmp = b->ntmp + off;
             off += (int64_t)im.g.rows * im.g.cols;
             ntile_start.push_back(ntile_start.back() + normal_tiles(im.g));
@@ -343,6 +384,10 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
         e = hipMemcpy(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_pre_start, pre_start.data(), pre_start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_pre_need_start, pre_need_start.data(), pre_need_start.size() * sizeof(int),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_need, need.data(), (size_t)n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->state, 0, (size_t)n * 2 * sizeof(RegState));
     if (e == hipSuccess) e = hipMemset(b->sched, 0, sizeof(Sched));  // epoch 0: no ticket carries a tile yet
     if (e == hipSuccess) e = hipMemset(b->tile_map, 0, (size_t)b->map_size * sizeof(unsigned long long));
@@ -423,6 +468,14 @@ ups_status ups_batch_set_scheduler(ups_batch *b, int32_t scheduler) {
     return UPS_OK;
 }
 
+ups_status ups_batch_set_pyramid_mode(ups_batch *b, int32_t mode) {
+    UPS_REQUIRE(b, "null argument");
+    UPS_REQUIRE(mode == UPS_PYR_IN_REGISTER || mode == UPS_PYR_IN_NORMALS,
+                "mode must be UPS_PYR_IN_REGISTER or UPS_PYR_IN_NORMALS");
+    b->pyr_mode = mode;
+    return UPS_OK;
+}
+
 ups_status ups_batch_set_iterations(ups_batch *b, const int32_t iters[4]) {
     UPS_REQUIRE(b && iters, "null argument");
     for (int l = 0; l < b->p.levels; l++)
@@ -446,7 +499,9 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
     DeviceGuard dg(ctx->device);
     UPS_CHECK_HIP(dg.err);
     if (b->n_nimg == 0) return UPS_OK;
-    return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p, (hipStream_t)stream);
+    // in UPS_PYR_IN_NORMALS mode the last pass also writes the images' pyramids
+    return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p,
+                                b->pyr_mode == UPS_PYR_IN_NORMALS ? 1 : 0, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -461,8 +516,8 @@ ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_re
     ups_status st;
     const ups_icp_params &p = b->p;
     const int n = b->n;
-    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, nullptr, s)) !=
-        UPS_OK)
+    const PyrWork pw = pyramid_work(b);
+    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, pw.start, pw.total, nullptr, pw.need, s)) != UPS_OK)
         return st;
     StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -509,7 +564,7 @@ ups_status register_batch_subset(ups_batch *b, const ups_pose *init_d, const uin
     ups_icp_params p = b->p;  // the schedule the batch was created with
     for (int l = 0; l < 4; l++) p.iters[l] = b->iters_full[l];
     const int n = b->n;
-    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, b->total_pre, mask, s)) != UPS_OK)
+    if ((st = launch_prepare_batch(b->d_inst, init_d, n, p.levels, b->d_pre_start, 0, mask, nullptr, s)) != UPS_OK)
         return st;
     StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -555,8 +610,8 @@ ups_status register_batch_persistent(ups_batch *b, const ups_pose *init_d, const
                                hipStream_t s) {
     ups_status st;
     const ups_icp_params &p = b->p;
-    if ((st = launch_prepare_batch(b->d_inst, init_d, b->n, p.levels, b->d_pre_start, b->total_pre, mask, s)) !=
-        UPS_OK)
+    const PyrWork pw = pyramid_work(b);
+    if ((st = launch_prepare_batch(b->d_inst, init_d, b->n, p.levels, pw.start, pw.total, mask, pw.need, s)) != UPS_OK)
         return st;
     SchedArgs A;
     memset(&A, 0, sizeof(A));
@@ -639,7 +694,8 @@ ups_status ups_batch_grid_search(ups_context *ctx, ups_batch *b, const ups_grid_
     UPS_CHECK_HIP(dg.err);
     hipStream_t s = (hipStream_t)stream;
     const int n = b->n, l = gp->level;
-    if (l > 0 && (st = launch_build_pyramids(b->d_inst, n, b->p.levels, b->d_pre_start, b->total_pre, s)) != UPS_OK)
+    const PyrWork pw = pyramid_work(b);
+    if (l > 0 && (st = launch_build_pyramids(b->d_inst, n, b->p.levels, pw.start, pw.total, pw.need, s)) != UPS_OK)
         return st;
     GridArgs g;
     g.level = l;

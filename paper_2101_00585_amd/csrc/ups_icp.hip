@@ -50,10 +50,13 @@ __device__ __forceinline__ void pyramid_from_level1(const DGeom *g, const float4
 // through the prefix table of per-registration level-1 pixel counts (scan,
 // then keyframe).
 // With a mask, registrations whose mask byte is 0 are marked to skip the call.
+// With need, only the images need[k] names (bit 0 the scan, bit 1 the
+// keyframe) are built, and pix_start counts only their level-1 pixels.
 __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict__ insts, const ups_pose *init,
                                                           int n, int levels, int init_blocks,
                                                           const int *__restrict__ pix_start,
-                                                          const uint8_t *__restrict__ mask) {
+                                                          const uint8_t *__restrict__ mask,
+                                                          const uint8_t *__restrict__ need) {
     if ((int)blockIdx.x < init_blocks) {
         const int k = blockIdx.x * kBlock + threadIdx.x;
         if (k >= n) return;
@@ -82,30 +85,33 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batch(const Inst *__restrict
     }
     const Inst &I = insts[lo];
     const int q = t - pix_start[lo];
-    const int n0 = I.sg[1].rows * I.sg[1].cols;
+    const int n0 = (need && !(need[lo] & 1)) ? 0 : I.sg[1].rows * I.sg[1].cols;
     if (q < n0) pyramid_from_level1(I.sg, I.scan, levels, q);
     else pyramid_from_level1(I.kg, I.kf, levels, q - n0);
 }
 
 // mask: null = every registration, pyramids built; else only the masked-in
-// registrations run and the pyramids of the previous call are reused.
+// registrations run and the pyramids of the previous call are reused.  need:
+// null = every image's pyramid, else those of the images need[k] names
+// (pix_start / total_pix count their level-1 pixels; 0: the states only).
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
-                                int total_pix, const uint8_t *mask, hipStream_t s) {
+                                int total_pix, const uint8_t *mask, const uint8_t *need, hipStream_t s) {
     const int ib = (n + kBlock - 1) / kBlock;
     const int pb = mask ? 0 : (total_pix + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_prepare_batch, dim3(ib + pb), dim3(kBlock), 0, s, insts, init, n, levels, ib, pix_start,
-                       mask);
+                       mask, need);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }
 
-// The pyramids alone (no registration state is touched).
+// The pyramids alone (no registration state is touched); with need, those of
+// the images need[k] names only (pix_start then counts their pixels).
 ups_status launch_build_pyramids(const Inst *insts, int n, int levels, const int *pix_start, int total_pix,
-                                 hipStream_t s) {
+                                 const uint8_t *need, hipStream_t s) {
     const int pb = (total_pix + kBlock - 1) / kBlock;
     if (pb == 0) return UPS_OK;
     hipLaunchKernelGGL(k_prepare_batch, dim3(pb), dim3(kBlock), 0, s, insts, (const ups_pose *)nullptr, n, levels, 0,
-                       pix_start, (const uint8_t *)nullptr);
+                       pix_start, (const uint8_t *)nullptr, need);
     UPS_CHECK_HIP(hipGetLastError());
     return UPS_OK;
 }

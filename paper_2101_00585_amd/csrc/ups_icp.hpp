@@ -136,7 +136,7 @@ ups_status launch_grid_search(const Inst *insts, const int *tile_start_l, int n,
                               const ups_pose *base, const GridArgs &g, int *scores, ups_pose *best, int *best_score,
                               hipStream_t s);
 ups_status launch_build_pyramids(const Inst *insts, int n, int levels, const int *pix_start, int total_pix,
-                                 hipStream_t s);
+                                 const uint8_t *need, hipStream_t s);
 ups_status launch_register(const Inst &I, const ups_pose *init, const ups_icp_params &p, hipStream_t s);
 ups_status launch_correspondences_world(const DGeom &sg, const float4 *scan, const DGeom &kg, const float4 *kf,
                                         const ups_pose *T, const ups_pose &world_kf, float d_max, float cos_theta,
@@ -185,7 +185,7 @@ ups_status launch_finish_batch_list(int prec, const Inst *insts, const Compact *
 ups_status launch_finish_batch(int prec, const Inst *insts, int n, int parity, ups_icp_result *results,
                                hipStream_t s);
 ups_status launch_prepare_batch(const Inst *insts, const ups_pose *init, int n, int levels, const int *pix_start,
-                                int total_pix, const uint8_t *mask, hipStream_t s);
+                                int total_pix, const uint8_t *mask, const uint8_t *need, hipStream_t s);
 ups_status launch_fallback_plan(int n, const ups_icp_result *res, double min_ratio, const int *tile_start,
                                 uint8_t *mask, Compact *hdr, int *list, int *start, int32_t *count, hipStream_t s);
 ups_status launch_icp_batch_list(int K, int prec, int mode, const Inst *insts, const Compact *hdr, const int *list,

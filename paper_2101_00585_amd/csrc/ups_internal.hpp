@@ -106,13 +106,15 @@ int autotuned_k(ups_context *ctx, int64_t npix);
 struct NormImg {
     DGeom g;
     const float *depth;
-    float4 *out;  // surfel image
-    float4 *tmp;  // a-trous ping-pong buffer of the same size
+    float4 *out;     // surfel image
+    float4 *tmp;     // a-trous ping-pong buffer of the same size
+    float4 *pyr[3];  // its pyramid levels 1-3 (null past the batch's levels)
 };
 
 int normal_tiles(const DGeom &g);
+// write_pyr: the last pass also writes every image's pyramid levels (pyr).
 ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
-                                const ups_normal_params &p, hipStream_t s);
+                                const ups_normal_params &p, int write_pyr, hipStream_t s);
 
 // launchers (each returns UPS_OK or sets the error)
 ups_status launch_normals(ups_context *ctx, const DGeom &g, const float *depth, float4 *surfel,

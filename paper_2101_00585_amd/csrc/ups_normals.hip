@@ -113,6 +113,17 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
     return o;
 }
 
+// Pyramid levels 1-3 of an image from its level-0 pixel (i, j): level-l pixel
+// (i >> l, j >> l) when i and j are multiples of 2^l (every 2^l-th row and
+// column; pyr[l - 1] null past the last level).
+__device__ __forceinline__ void store_pyramid(const DGeom &g, float4 *const *pyr, int i, int j, float4 v) {
+#pragma unroll
+    for (int l = 1; l <= 3; l++) {
+        float4 *dst = pyr[l - 1];
+        if (dst && ((i | j) & ((1 << l) - 1)) == 0) dst[(i >> l) * (g.cols >> l) + (j >> l)] = v;
+    }
+}
+
 // One a-trous level with taps spaced STEP for the kTileH x 64 output tile at
 // (x0, y0): the block stages the (kTileH + 4 STEP) x (64 + 4 STEP) surfel
 // tile around it in LDS (rows outside the image empty, columns wrapped), one
@@ -121,7 +132,8 @@ __device__ __forceinline__ float4 atrous_tap_sum(const float4 *tile, int LW, int
 // constant offset from the output's address.
 template <int kTileH, int STEP>
 __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__restrict__ in, float4 *__restrict__ out,
-                                            int x0, int y0, float inv_sigma_r, float inv_sigma_n2, float4 *tile) {
+                                            int x0, int y0, float inv_sigma_r, float inv_sigma_n2, float4 *tile,
+                                            float4 *const *pyr) {
     constexpr int halo = 2 * STEP;
     constexpr int LW = kTileW + 2 * halo, LH = kTileH + 2 * halo;
     for (int idx = threadIdx.x; idx < LW * LH; idx += kBlock) {
@@ -138,7 +150,9 @@ __device__ __forceinline__ void atrous_tile(const DGeom &g, const float4 *__rest
     for (int ty = threadIdx.x / kTileW; ty < kTileH; ty += kBlock / kTileW) {
         const int gy = y0 + ty;
         if (gy >= g.rows) break;
-        out[gy * g.cols + x0 + tx] = atrous_tap_sum(tile, LW, ty, tx, STEP, inv_sigma_r, inv_sigma_n2);
+        const float4 v = atrous_tap_sum(tile, LW, ty, tx, STEP, inv_sigma_r, inv_sigma_n2);
+        out[gy * g.cols + x0 + tx] = v;
+        if (pyr) store_pyramid(g, pyr, gy, x0 + tx, v);
     }
 }
 
@@ -150,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__rest
                                                    float inv_sigma_r, float inv_sigma_n2) {
     __shared__ float4 tile[atrous_tile_elems<kTileHOne, STEP>()];
     atrous_tile<kTileHOne, STEP>(g, in, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, inv_sigma_r, inv_sigma_n2,
-                                 tile);
+                                 tile, nullptr);
 }
 
 // Raw normals and the first a-trous level (step 1) in one pass: the block
@@ -160,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_atrous(DGeom g, const float4 *__rest
 template <int kTileH>
 __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float *__restrict__ depth,
                                                     float4 *__restrict__ out, int x0, int y0, float max_rel_jump,
-                                                    float inv_sigma_r, float inv_sigma_n2) {
+                                                    float inv_sigma_r, float inv_sigma_n2, float4 *const *pyr) {
     constexpr int kFH = kTileH + 4, kFW = kTileW + 4;  // raw-normal tile
     constexpr int kDH = kFH + 2, kDW = kFW + 1;        // range tile: one row above and below, one column right
     static_assert(kDH + kDW <= kBlock, "ray tables of the tile: one entry per thread");
@@ -209,7 +223,9 @@ __device__ __forceinline__ void normals_atrous_tile(const DGeom &g, const float 
     for (int ty = threadIdx.x / kTileW; ty < kTileH; ty += kBlock / kTileW) {
         const int gy = y0 + ty;
         if (gy >= g.rows) break;
-        out[gy * g.cols + x0 + tx] = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
+        const float4 v = atrous_tap_sum(raw, kFW, ty, tx, 1, inv_sigma_r, inv_sigma_n2);
+        out[gy * g.cols + x0 + tx] = v;
+        if (pyr) store_pyramid(g, pyr, gy, x0 + tx, v);
     }
 }
 
@@ -217,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float 
                                                            float4 *__restrict__ out, float max_rel_jump,
                                                            float inv_sigma_r, float inv_sigma_n2) {
     normals_atrous_tile<kTileHOne>(g, depth, out, blockIdx.x * kTileW, blockIdx.y * kTileHOne, max_rel_jump,
-                                   inv_sigma_r, inv_sigma_n2);
+                                   inv_sigma_r, inv_sigma_n2, nullptr);
 }
 
 // ---- batched: block -> (image, tile) through the prefix table of tile counts
@@ -234,34 +250,34 @@ __device__ __forceinline__ int find_image(const int *__restrict__ tile_start, in
 
 __global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *__restrict__ imgs,
                                                                  const int *__restrict__ tile_start, int n,
-                                                                 int out_tmp, float max_rel_jump, float inv_sigma_r,
-                                                                 float inv_sigma_n2) {
+                                                                 int out_tmp, int write_pyr, float max_rel_jump,
+                                                                 float inv_sigma_r, float inv_sigma_n2) {
     const int k = find_image(tile_start, n, blockIdx.x);
     const NormImg &im = imgs[k];
     const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
     normals_atrous_tile<kTileHBatch>(im.g, im.depth, out_tmp ? im.tmp : im.out, bx * kTileW, by * kTileHBatch,
-                                     max_rel_jump, inv_sigma_r, inv_sigma_n2);
+                                     max_rel_jump, inv_sigma_r, inv_sigma_n2, write_pyr ? im.pyr : nullptr);
 }
 
 template <int STEP>
 __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restrict__ imgs,
                                                          const int *__restrict__ tile_start, int n, int src_tmp,
-                                                         float inv_sigma_r, float inv_sigma_n2) {
+                                                         int write_pyr, float inv_sigma_r, float inv_sigma_n2) {
     __shared__ float4 tile[atrous_tile_elems<kTileHBatch, STEP>()];
     const int k = find_image(tile_start, n, blockIdx.x);
     const NormImg &im = imgs[k];
     const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
     atrous_tile<kTileHBatch, STEP>(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW,
-                                   by * kTileHBatch, inv_sigma_r, inv_sigma_n2, tile);
+                                   by * kTileHBatch, inv_sigma_r, inv_sigma_n2, tile, write_pyr ? im.pyr : nullptr);
 }
 
 // Tiles of a panorama in the batched a-trous launches.
 int normal_tiles(const DGeom &g) { return (g.cols / kTileW) * ((g.rows + kTileHBatch - 1) / kTileHBatch); }
 
 ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
-                                const ups_normal_params &p, hipStream_t s) {
+                                const ups_normal_params &p, int write_pyr, hipStream_t s) {
     const int L = p.atrous_levels;
     const float inv_sr = 1.f / p.sigma_r, inv_sn2 = 1.f / (p.sigma_n * p.sigma_n);
     if (L == 0 || total_tiles == 0) {
@@ -273,17 +289,19 @@ ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int 
     }
     // ping-pong between out and tmp so that the last level writes out
     int in_tmp = (L - 1) % 2;
+    // the last pass writes the surfel images (and, with write_pyr, their pyramids)
     hipLaunchKernelGGL(k_normals_atrous_batch, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
-                       p.max_rel_jump, inv_sr, inv_sn2);
+                       (L == 1) ? write_pyr : 0, p.max_rel_jump, inv_sr, inv_sn2);
     UPS_CHECK_HIP(hipGetLastError());
     for (int l = 1; l < L; l++) {
         // levels 1 and 2 (taps spaced 2 and 4); the caller limits the levels to 3
+        const int last = (l == L - 1) ? write_pyr : 0;
         if (l == 1)
             hipLaunchKernelGGL(k_atrous_batch<2>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
-                               inv_sr, inv_sn2);
+                               last, inv_sr, inv_sn2);
         else
             hipLaunchKernelGGL(k_atrous_batch<4>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
-                               inv_sr, inv_sn2);
+                               last, inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         in_tmp ^= 1;
     }

@@ -197,7 +197,7 @@ extern "C" ups_status ups_autotune(ups_context *ctx, const char *cache_json_path
                 (void)hipFree(d_pre);
                 break;
             }
-            result = launch_prepare_batch(d_inst, d_init, copies, 1, d_pre, 0, nullptr, s);
+            result = launch_prepare_batch(d_inst, d_init, copies, 1, d_pre, 0, nullptr, nullptr, s);
             StepArgs a;
             memset(&a, 0, sizeof(a));
             a.level = 0;

@@ -74,6 +74,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert rc == -1
     rc = L.ups_classify_loop_closures(None, 4, None, 0.5, None, None, None)
     assert rc == -1
+    assert L.ups_batch_set_pyramid_mode(None, 1) == -1
 
 
 def test_conv_arguments_rejected_on_host(lib):

@@ -318,3 +318,64 @@ def test_benchmark_batch_sampled_against_oracle(gpu_lib, bctx):
         dr = pose_displacement_bound(res[k]["T"], ref["T"], float(scan[..., 3].max()))
         print(f"   truncated cost {res[k]['trunc_cost']:.6f} / {ref['trunc_cost']:.6f}, mismatches {mism}", flush=True)
         assert_quality_close(res[k], ref, mism, 0.5, dr, float(np.abs(rr["r"][rr["inlier"]]).sum()))
+
+
+def test_pyramids_built_by_normals_give_the_same_results(gpu_lib, bctx, pairs):
+    """UPS_PYR_IN_NORMALS: the normals' last pass writes the pyramids of the
+    images it computes (every scan, the keyframes with depth), and register
+    and grid search build only those of the keyframes given as surfels.
+    Results bitwise those of the default mode (both batches alive at once, so
+    the second's pyramid memory is fresh), also from a captured graph
+    replayed three times, and grid-search scores equal."""
+    import torch
+    items = _items_from_depth(gpu_lib, pairs)
+    # every other keyframe resident (surfels only): its pyramid comes from the side stream
+    for k, it in enumerate(items):
+        gpu_lib.panorama_normals(bctx, it["kf_geom"], it["kf_depth"], it["kf_surfel"])
+    items2 = [dict(it) for it in items]
+    for k, it in enumerate(items2):
+        it["scan_surfel"] = torch.empty_like(it["scan_surfel"])
+        if k % 2:
+            it.pop("kf_depth")
+        else:
+            it["kf_surfel"] = torch.empty_like(it["kf_surfel"])
+    params = gpu_lib.IcpParams(**BATCH_PARAMS)
+    ref_b = gpu_lib.Batch(bctx, items, params)
+    b = gpu_lib.Batch(bctx, items2, params)
+    b.set_pyramid_mode(True)
+    n = len(items)
+    init = torch.stack([gpu_lib.pose_tensor(np.eye(4)) for _ in items])
+    ref_b.normals()
+    ref = _np(ref_b.register(init)).copy()
+    def grid(batch):
+        _, _, scores = batch.grid_search(base=init)
+        torch.cuda.synchronize()
+        return _np(scores)
+    ref_scores = grid(ref_b)
+    b.normals()
+    got = _np(b.register(init))
+    assert np.array_equal(got, ref)
+    assert np.array_equal(grid(b), ref_scores)
+    # captured: normals (writing the pyramids) and register
+    res = torch.zeros_like(torch.from_numpy(ref)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.normals()
+        b.register(init, res)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=s):
+        b.normals()
+        b.register(init, res)
+    for rep in range(3):
+        res.zero_()
+        for it in items2:
+            it["scan_surfel"].zero_()
+        torch.cuda.synchronize()
+        print(f"replay {rep}", flush=True)
+        with torch.cuda.stream(s):
+            gr.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(res), ref), rep
+    b.close()
+    ref_b.close()
