@@ -377,5 +377,11 @@ def test_pyramids_built_by_normals_give_the_same_results(gpu_lib, bctx, pairs):
             gr.replay()
         torch.cuda.synchronize()
         assert np.array_equal(_np(res), ref), rep
+    # the persistent scheduler reads the same pyramids
+    for batch in (ref_b, b):
+        batch.set_scheduler(True)
+    ref_p = _np(ref_b.register(init)).copy()
+    b.normals()
+    assert np.array_equal(_np(b.register(init)), ref_p)
     b.close()
     ref_b.close()
