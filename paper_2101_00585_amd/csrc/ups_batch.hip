@@ -35,6 +35,8 @@ struct ups_batch {
     int total_pre = 0;
     Inst *d_inst = nullptr;       // [n]
     int *d_tile_start = nullptr;  // [4][n+1]
+    unsigned *d_tile_of = nullptr;  // per level, (registration << 16) | tile of each tile (StepArgs::tile_of)
+    int64_t tile_of_off[4] = {0, 0, 0, 0};
     int *d_pre_start = nullptr;   // [n+1]
     float4 *pyr = nullptr;
     RegState *state = nullptr;    // [n][2]
@@ -91,6 +93,7 @@ namespace {
 void free_batch(ups_batch *b) {
     (void)hipFree(b->d_inst);
     (void)hipFree(b->d_tile_start);
+    (void)hipFree(b->d_tile_of);
     (void)hipFree(b->d_pre_start);
     (void)hipFree(b->pyr);
     (void)hipFree(b->state);
@@ -144,6 +147,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     UPS_REQUIRE(ctx && items && p && out, "null argument");
     *out = nullptr;
     UPS_REQUIRE(n >= 1 && n <= ctx->max_batch, "n must be in [1, the context's max_batch]");
+    UPS_REQUIRE(n <= 65535, "a batch holds at most 65535 registrations");
     UPS_REQUIRE(pixels_per_thread == 0 || (pixels_per_thread <= 64 && (pixels_per_thread & (pixels_per_thread - 1)) == 0),
                 "pixels_per_thread must be 0 or a power of two up to 64");
     {
@@ -297,6 +301,16 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     };
     alloc((void **)&b->d_inst, n * sizeof(Inst));
     alloc((void **)&b->d_tile_start, tile_start.size() * sizeof(int));
+    // block -> (registration, tile) of every level, so that a block finds its
+    // tile with one load
+    std::vector<unsigned> tile_of;
+    for (int l = 0; l < 4; l++) {
+        b->tile_of_off[l] = (int64_t)tile_of.size();
+        for (int k = 0; k < n; k++)
+            for (int t = tile_start[l * (n + 1) + k]; t < tile_start[l * (n + 1) + k + 1]; t++)
+                tile_of.push_back(((unsigned)k << 16) | (unsigned)(t - tile_start[l * (n + 1) + k]));
+    }
+    alloc((void **)&b->d_tile_of, std::max<size_t>(tile_of.size(), 1) * sizeof(unsigned));
     alloc((void **)&b->d_pre_start, pre_start.size() * sizeof(int));
     alloc((void **)&b->pyr, std::max<int64_t>(pyr_total, 1) * sizeof(float4));
     alloc((void **)&b->state, (size_t)n * 2 * sizeof(RegState));
@@ -382,6 +396,8 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_tile_start, tile_start.data(), tile_start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tile_of.empty())
+        e = hipMemcpy(b->d_tile_of, tile_of.data(), tile_of.size() * sizeof(unsigned), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->d_pre_start, pre_start.data(), pre_start.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -429,6 +445,7 @@ ups_status ups_batch_time_iteration(ups_context *ctx, ups_batch *b, int32_t leve
     a.cos_theta = b->p.cos_theta_max;
     a.irls_delta = b->p.irls_delta;
     a.min_inliers = b->p.min_inliers;
+    a.tile_of = b->d_tile_of + b->tile_of_off[level];
     ups_status st;
     if ((st = launch_activate_batch(b->d_inst, b->n, s)) != UPS_OK) return st;
     hipEvent_t e0, e1;
@@ -530,6 +547,7 @@ ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_re
     for (int l = p.levels - 1; l >= 0; l--) {
         a.level = l;
         a.d_max2 = p.d_max[l] * p.d_max[l];
+        a.tile_of = b->d_tile_of + b->tile_of_off[l];
         for (int it = 0; it < p.iters[l]; it++) {
             a.parity = parity;
             a.first_of_level = it == 0;
@@ -546,6 +564,7 @@ ups_status register_batch_fused(ups_batch *b, const ups_pose *init_d, ups_icp_re
     a.d_max2 = p.d_max[0] * p.d_max[0];
     a.tau2 = a.d_max2;
     a.check_max_iters = (p.stop_update_norm > 0.0 && p.iters[0] > 0);
+    a.tile_of = b->d_tile_of + b->tile_of_off[0];
     if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, n, a, b->total_tiles[0],
                                s, true)) != UPS_OK)
         return st;
@@ -649,6 +668,7 @@ ups_status register_batch_persistent(ups_batch *b, const ups_pose *init_d, const
     e.irls_delta = p.irls_delta;
     e.min_inliers = p.min_inliers;
     e.stop_norm = p.stop_update_norm;
+    e.tile_of = b->d_tile_of + b->tile_of_off[0];
     if ((st = launch_icp_batch(b->K[0], p.precision, MODE_EVAL, b->d_inst, b->d_tile_start, b->n, e, b->total_tiles[0],
                                s)) != UPS_OK)
         return st;

@@ -71,6 +71,9 @@ struct StepArgs {
     const ups_pose *init;  // single registrations: the first launch builds the state from this start pose
     int reverse_tiles;  // debug: workgroups take the tiles in reverse order (set by the launchers)
     int seq;            // single registrations: the launch's number within the call (phase timestamps)
+    // batches: (registration << 16) | tile of each of the level's tiles in tile
+    // order (null: found by binary search in the prefix table of tile counts)
+    const unsigned *tile_of;
 };
 
 // Debug tile order of the iteration / evaluation launches (ups_debug_reverse_tile_order).

@@ -1044,14 +1044,21 @@ __global__ __launch_bounds__(kBlock) void k_icp_level_xcd(Inst I, StepArgs a, in
     if (tile == 0 && tid == 0) I.state[(a.parity + iters) & 1] = sh.S;
 }
 
-// Batch: block -> (registration, tile) by binary search in the level's prefix
-// table of tile counts (tile_start[n] = total blocks).  FUSED: each block
-// first applies its registration's pending update (the batch's main loop);
-// otherwise slot 0 holds the pose (the subset and scheduled paths, timing).
+// Batch: block -> (registration, tile) from the level's table a.tile_of (one
+// load), or by binary search in the level's prefix table of tile counts
+// (tile_start[n] = total blocks; a chain of dependent loads at the head of
+// every block).  FUSED: each block first applies its registration's pending
+// update (the batch's main loop); otherwise slot 0 holds the pose (the
+// subset and scheduled paths, timing).
 template <int K, int PREC, int MODE, bool IRLS, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_icp_batch(const Inst *__restrict__ insts,
                                                       const int *__restrict__ tile_start, int n, StepArgs a) {
     const int b = xcd_tile(blockIdx.x, gridDim.x, a.reverse_tiles);
+    if (a.tile_of) {
+        const unsigned v = a.tile_of[b];
+        icp_block<K, PREC, MODE, FUSED, false, IRLS, false>(insts[v >> 16], a, (int)(v & 0xFFFFu));
+        return;
+    }
     int lo = 0, hi = n;  // the last k with tile_start[k] <= b
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
