@@ -43,7 +43,7 @@ struct ups_batch {
     double *partials = nullptr;   // [n][2][kPartialStride][pstride]
     // batched normals
     NormImg *d_nimg = nullptr;
-    int *d_ntile_start = nullptr;
+    unsigned *d_ntile_of = nullptr;  // [total_ntiles]: (image << kNormTileBits) | tile
     float4 *ntmp = nullptr;
     int n_nimg = 0, total_ntiles = 0;
     // identity-started fallback
@@ -99,7 +99,7 @@ void free_batch(ups_batch *b) {
     (void)hipFree(b->state);
     (void)hipFree(b->partials);
     (void)hipFree(b->d_nimg);
-    (void)hipFree(b->d_ntile_start);
+    (void)hipFree(b->d_ntile_of);
     (void)hipFree(b->ntmp);
     (void)hipFree(b->ident);
     (void)hipFree(b->mask);
@@ -279,7 +279,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     // batched-normals images: every scan / keyframe with a depth pointer
     std::vector<NormImg> nimg;
     std::vector<std::pair<int, int>> nimg_of;  // (registration, 0 scan / 1 keyframe) of each entry
-    std::vector<int> ntile_start(1, 0);
+    std::vector<unsigned> ntile_of;
     int64_t ntmp_total = 0;
     for (int k = 0; k < n; k++) {
         const ups_batch_item &it = items[k];
@@ -375,11 +375,17 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
                 im.pyr[l - 1] = l < L ? (float4 *)(nimg_of[m].second == 0 ? I.scan[l] : I.kf[l]) : nullptr;
             im.tmp = b->ntmp + off;
             off += (int64_t)im.g.rows * im.g.cols;
-            ntile_start.push_back(ntile_start.back() + normal_tiles(im.g));
+            const int nt = normal_tiles(im.g);
+            if (nt >= (1 << kNormTileBits)) {
+                free_batch(b);
+                set_error("panorama with too many normal tiles for a batch (at most 8191 tiles of 64 x 16 pixels)");
+                return UPS_ERR_INVALID_ARG;
+            }
+            for (int t = 0; t < nt; t++) ntile_of.push_back(((unsigned)m << kNormTileBits) | (unsigned)t);
         }
         b->n_nimg = (int)nimg.size();
-        b->total_ntiles = ntile_start.back();
-        alloc((void **)&b->d_ntile_start, ntile_start.size() * sizeof(int));
+        b->total_ntiles = (int)ntile_of.size();
+        alloc((void **)&b->d_ntile_of, ntile_of.size() * sizeof(unsigned));
     }
     if (e == hipSuccess) e = hipMemcpy(b->d_inst, hi.data(), n * sizeof(Inst), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
@@ -410,8 +416,7 @@ ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *i
     if (e == hipSuccess && !nimg.empty()) {
         e = hipMemcpy(b->d_nimg, nimg.data(), nimg.size() * sizeof(NormImg), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(b->d_ntile_start, ntile_start.data(), ntile_start.size() * sizeof(int),
-                          hipMemcpyHostToDevice);
+            e = hipMemcpy(b->d_ntile_of, ntile_of.data(), ntile_of.size() * sizeof(unsigned), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -517,7 +522,7 @@ ups_status ups_batch_normals(ups_context *ctx, ups_batch *b, const ups_normal_pa
     UPS_CHECK_HIP(dg.err);
     if (b->n_nimg == 0) return UPS_OK;
     // in UPS_PYR_IN_NORMALS mode the last pass also writes the images' pyramids
-    return launch_normals_batch(b->d_nimg, b->d_ntile_start, b->n_nimg, b->total_ntiles, *p,
+    return launch_normals_batch(b->d_nimg, b->d_ntile_of, b->total_ntiles, *p,
                                 b->pyr_mode == UPS_PYR_IN_NORMALS ? 1 : 0, (hipStream_t)stream);
 }
 

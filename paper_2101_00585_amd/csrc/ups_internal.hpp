@@ -111,9 +111,13 @@ struct NormImg {
     float4 *pyr[3];  // its pyramid levels 1-3 (null past the batch's levels)
 };
 
+// Tiles of a panorama in the batched a-trous launches (at most 2^kNormTileBits:
+// 64-pixel-wide tiles of 16 rows, cols <= 8192, rows <= 1024).
 int normal_tiles(const DGeom &g);
+constexpr int kNormTileBits = 13;
+// tile_of[b]: (image << kNormTileBits) | tile of the image, for every block b.
 // write_pyr: the last pass also writes every image's pyramid levels (pyr).
-ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
+ups_status launch_normals_batch(const NormImg *imgs, const unsigned *tile_of, int total_tiles,
                                 const ups_normal_params &p, int write_pyr, hipStream_t s);
 
 // launchers (each returns UPS_OK or sets the error)

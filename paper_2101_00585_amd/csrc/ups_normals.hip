@@ -236,25 +236,16 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous(DGeom g, const float 
                                    inv_sigma_r, inv_sigma_n2, nullptr);
 }
 
-// ---- batched: block -> (image, tile) through the prefix table of tile counts
-
-__device__ __forceinline__ int find_image(const int *__restrict__ tile_start, int n, int b) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tile_start[mid] <= b) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
+// ---- batched: block -> (image, tile) from a table, one word per tile:
+// (image << kNormTileBits) | tile of the image
 
 __global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *__restrict__ imgs,
-                                                                 const int *__restrict__ tile_start, int n,
+                                                                 const unsigned *__restrict__ tile_of,
                                                                  int out_tmp, int write_pyr, float max_rel_jump,
                                                                  float inv_sigma_r, float inv_sigma_n2) {
-    const int k = find_image(tile_start, n, blockIdx.x);
-    const NormImg &im = imgs[k];
-    const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
+    const unsigned v = tile_of[blockIdx.x];
+    const NormImg &im = imgs[v >> kNormTileBits];
+    const int t = (int)(v & ((1u << kNormTileBits) - 1)), tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
     normals_atrous_tile<kTileHBatch>(im.g, im.depth, out_tmp ? im.tmp : im.out, bx * kTileW, by * kTileHBatch,
                                      max_rel_jump, inv_sigma_r, inv_sigma_n2, write_pyr ? im.pyr : nullptr);
@@ -262,12 +253,12 @@ __global__ __launch_bounds__(kBlock) void k_normals_atrous_batch(const NormImg *
 
 template <int STEP>
 __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restrict__ imgs,
-                                                         const int *__restrict__ tile_start, int n, int src_tmp,
+                                                         const unsigned *__restrict__ tile_of, int src_tmp,
                                                          int write_pyr, float inv_sigma_r, float inv_sigma_n2) {
     __shared__ float4 tile[atrous_tile_elems<kTileHBatch, STEP>()];
-    const int k = find_image(tile_start, n, blockIdx.x);
-    const NormImg &im = imgs[k];
-    const int t = blockIdx.x - tile_start[k], tx = im.g.cols / kTileW;
+    const unsigned v = tile_of[blockIdx.x];
+    const NormImg &im = imgs[v >> kNormTileBits];
+    const int t = (int)(v & ((1u << kNormTileBits) - 1)), tx = im.g.cols / kTileW;
     const int by = t / tx, bx = t - by * tx;
     atrous_tile<kTileHBatch, STEP>(im.g, src_tmp ? im.tmp : im.out, src_tmp ? im.out : im.tmp, bx * kTileW,
                                    by * kTileHBatch, inv_sigma_r, inv_sigma_n2, tile, write_pyr ? im.pyr : nullptr);
@@ -276,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_atrous_batch(const NormImg *__restri
 // Tiles of a panorama in the batched a-trous launches.
 int normal_tiles(const DGeom &g) { return (g.cols / kTileW) * ((g.rows + kTileHBatch - 1) / kTileHBatch); }
 
-ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int n, int total_tiles,
+ups_status launch_normals_batch(const NormImg *imgs, const unsigned *tile_of, int total_tiles,
                                 const ups_normal_params &p, int write_pyr, hipStream_t s) {
     const int L = p.atrous_levels;
     const float inv_sr = 1.f / p.sigma_r, inv_sn2 = 1.f / (p.sigma_n * p.sigma_n);
@@ -290,17 +281,17 @@ ups_status launch_normals_batch(const NormImg *imgs, const int *tile_start, int 
     // ping-pong between out and tmp so that the last level writes out
     int in_tmp = (L - 1) % 2;
     // the last pass writes the surfel images (and, with write_pyr, their pyramids)
-    hipLaunchKernelGGL(k_normals_atrous_batch, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+    hipLaunchKernelGGL(k_normals_atrous_batch, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_of, in_tmp,
                        (L == 1) ? write_pyr : 0, p.max_rel_jump, inv_sr, inv_sn2);
     UPS_CHECK_HIP(hipGetLastError());
     for (int l = 1; l < L; l++) {
         // levels 1 and 2 (taps spaced 2 and 4); the caller limits the levels to 3
         const int last = (l == L - 1) ? write_pyr : 0;
         if (l == 1)
-            hipLaunchKernelGGL(k_atrous_batch<2>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+            hipLaunchKernelGGL(k_atrous_batch<2>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_of, in_tmp,
                                last, inv_sr, inv_sn2);
         else
-            hipLaunchKernelGGL(k_atrous_batch<4>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_start, n, in_tmp,
+            hipLaunchKernelGGL(k_atrous_batch<4>, dim3(total_tiles), dim3(kBlock), 0, s, imgs, tile_of, in_tmp,
                                last, inv_sr, inv_sn2);
         UPS_CHECK_HIP(hipGetLastError());
         in_tmp ^= 1;
