@@ -378,9 +378,10 @@ typedef struct ups_batch ups_batch;
  * items, uploads their descriptors and allocates the batch's scratch
  * (pyramids, states, partials).  Synchronous; not for use during capture.
  * pixels_per_thread: a power of two up to 64, or 0 for the library's choice
- * (the autotuned value for these sizes if ups_autotune has run).  Every item
- * must satisfy the ups_register_scan constraints and have at most
- * 256 * 256 * 64 pixels. */
+ * (the autotuned value for these sizes if ups_autotune has run).  n is at
+ * most the context's max_batch and 65535.  Every item must satisfy the
+ * ups_register_scan constraints and have at most 256 * 256 * 64 pixels, and
+ * an item with depth at most 8191 normal tiles of 64 x 16 pixels. */
 ups_status ups_batch_create(ups_context *ctx, int32_t n, const ups_batch_item *items_h, const ups_icp_params *p,
                             int32_t pixels_per_thread, ups_batch **out);
 void ups_batch_destroy(ups_batch *b);
