@@ -821,12 +821,15 @@ __device__ __forceinline__ void icp_tile(const Inst &I, const StepArgs &a, int t
     ThreadAcc<PREC, NV> acc;
     acc.zero();
     int pw = pw0;
-    // groups of up to 4 pixels (the Kahan group), one group per trip of a
-    // loop that is not unrolled: at 32 pixels per thread the unrolled form is
-    // 118 KB of code, more than the instruction cache holds
+    // groups of up to 4 pixels (the Kahan group).  From 8 pixels per thread
+    // on, one group per trip of a loop that is not unrolled (unrolled, the
+    // 32-pixel batch kernel is 118 KB of code, more than the instruction cache
+    // holds); below, two groups per trip, so that the compensated sums need
+    // no register copies between trips
     constexpr int GP = K < 4 ? K : 4;
+    constexpr int kGroupUnroll = K >= 8 ? 1 : 2;
     bool done = false;
-#pragma clang loop unroll(disable)
+#pragma unroll kGroupUnroll
     for (int k0 = 0; k0 < KL; k0 += GP) {
 #pragma unroll
         for (int k = k0; k < k0 + GP; k += P) {
