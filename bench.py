@@ -49,9 +49,9 @@ HBM_PEAK_GBS = 8000.0
 # device copy in the same runs (FETCH_SIZE reads half the copy's bytes).  The
 # figures and commands are in profiles/icp_iteration_*.md; they hold only for
 # the kernel sources they were taken on (TRAFFIC_SRC_HASH), else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131092.56, 1.0
-TRAFFIC_KIB = {"single": (2081.95, 58.20), "batch": (497343.75, 1151.63)}
-TRAFFIC_SRC_HASH = "24b495b3528b3dc9"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.19, 1.0
+TRAFFIC_KIB = {"single": (2081.95, 58.20), "batch": (496590.50, 1187.97)}
+TRAFFIC_SRC_HASH = "979a6c18626c5f76"
 TRAFFIC_SRC = ("ups_icp_kernels.hpp", "ups_icp_iter_one.hip", "ups_icp_iter_batch.hip",
                "ups_icp_iter_batch_fused.hip", "ups_icp.hpp", "ups_device.hpp", "ups_internal.hpp")
 
